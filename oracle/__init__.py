@@ -1,0 +1,254 @@
+"""FP64 CPU oracle for STEV -- TEST INFRASTRUCTURE ONLY.
+
+Only the tests, ``__graft_entry__.smoke()`` and the benchmark's CPU-baseline
+leg may import this package.  The GPU library never loads it.
+
+The C sources (``stev_oracle.c``) implement the method literally; this module
+only builds them with gcc and marshals numpy arrays through ctypes.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "stev_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+def build(force=True):
+    """Compile the oracle with gcc (FP64, no FMA contraction, OpenMP)."""
+    cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math",
+           "-fopenmp", "-fPIC", "-shared", "-Wall", "-Wextra", "-o", _LIB + ".tmp",
+           _SRC, "-lm"]
+    if force or not os.path.exists(_LIB):
+        subprocess.check_call(cmd, cwd=_HERE)
+        os.replace(_LIB + ".tmp", _LIB)
+    return _LIB
+
+
+class _Mech(C.Structure):
+    _fields_ = [("n_s", C.c_int), ("n_r", C.c_int),
+                ("W", C.c_void_p), ("nasa_lo", C.c_void_p), ("nasa_hi", C.c_void_p),
+                ("T_mid", C.c_void_p), ("rxn_ptr", C.c_void_p), ("sp_idx", C.c_void_p),
+                ("nu", C.c_void_p), ("order", C.c_void_p), ("A", C.c_void_p),
+                ("b", C.c_void_p), ("Ea", C.c_void_p), ("rev", C.c_void_p)]
+
+
+class _Params(C.Structure):
+    _fields_ = [("ystep_max", C.c_double), ("delta_max", C.c_double),
+                ("alpha", C.c_double), ("tol_ring", C.c_double),
+                ("tol_freq", C.c_double), ("r_fac", C.c_double),
+                ("rof_min", C.c_double), ("dft_window", C.c_int), ("pad_", C.c_int),
+                ("max_iters", C.c_longlong)]
+
+
+DEFAULT_PARAMS = dict(ystep_max=1e-3, delta_max=1e-2, alpha=1e-5, tol_ring=0.5,
+                      tol_freq=1e-6, r_fac=2.0, rof_min=1e-12, dft_window=13,
+                      max_iters=1_000_000)
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        L = C.CDLL(_LIB)
+        dp = C.POINTER(C.c_double)
+        L.orc_thermo.argtypes = [C.POINTER(_Mech), C.c_int, C.c_double, dp]
+        L.orc_ystarstar.argtypes = [C.c_double, C.c_double]
+        L.orc_ystarstar.restype = C.c_double
+        L.orc_source.argtypes = [C.POINTER(_Mech), C.POINTER(_Params), C.c_double, C.c_double,
+                                 dp, dp, dp, dp, dp, dp, dp]
+        L.orc_step_size.argtypes = [C.POINTER(_Params), C.c_int, dp, dp, C.c_double, C.c_double]
+        L.orc_step_size.restype = C.c_double
+        L.orc_dft_mag.argtypes = [dp, C.c_int, dp]
+        L.orc_ringing_eq.argtypes = [dp, C.c_int, C.POINTER(_Params), dp]
+        L.orc_ringing_eq.restype = C.c_int
+        L.orc_rof_next.argtypes = [C.c_double, C.c_int, C.POINTER(_Params)]
+        L.orc_rof_next.restype = C.c_double
+        L.orc_integrate_cell.argtypes = [C.POINTER(_Mech), C.POINTER(_Params), dp, C.c_double,
+                                         dp, C.c_double, C.POINTER(C.c_longlong), dp, dp, dp,
+                                         C.c_longlong]
+        L.orc_integrate_cell.restype = C.c_int
+        L.orc_integrate.argtypes = [C.POINTER(_Mech), C.POINTER(_Params), C.c_longlong, dp, dp,
+                                    dp, C.c_longlong, C.c_double, C.POINTER(C.c_longlong),
+                                    C.POINTER(C.c_ubyte), dp, dp, C.c_int]
+        L.orc_integrate.restype = C.c_int
+        L.orc_nasa_targets.argtypes = [C.POINTER(_Mech), C.c_longlong, dp, dp, dp]
+        L.orc_mlp_n_params.argtypes = [C.c_int, C.c_int]
+        L.orc_mlp_n_params.restype = C.c_longlong
+        L.orc_mlp_forward.argtypes = [C.c_int, C.c_int, dp, C.c_longlong, dp, dp]
+        L.orc_mlp_loss_grad.argtypes = [C.c_int, C.c_int, dp, C.c_longlong, dp, dp, dp]
+        L.orc_mlp_loss_grad.restype = C.c_double
+        L.orc_adam_step.argtypes = [C.c_longlong, dp, dp, dp, dp, C.c_longlong, C.c_double,
+                                    C.c_double, C.c_double, C.c_double]
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+class OracleMech:
+    """Holds contiguous copies of a mechanism dict and the C view of them."""
+
+    def __init__(self, mech):
+        self.mech = mech
+        self._keep = {
+            "W": np.ascontiguousarray(mech["W"], dtype=np.float64),
+            "nasa_lo": np.ascontiguousarray(mech["nasa_lo"], dtype=np.float64),
+            "nasa_hi": np.ascontiguousarray(mech["nasa_hi"], dtype=np.float64),
+            "T_mid": np.ascontiguousarray(mech["T_mid"], dtype=np.float64),
+            "rxn_ptr": np.ascontiguousarray(mech["rxn_ptr"], dtype=np.int32),
+            "sp_idx": np.ascontiguousarray(mech["sp_idx"], dtype=np.int32),
+            "nu": np.ascontiguousarray(mech["nu"], dtype=np.float64),
+            "order": np.ascontiguousarray(mech["order"], dtype=np.float64),
+            "A": np.ascontiguousarray(mech["A"], dtype=np.float64),
+            "b": np.ascontiguousarray(mech["b"], dtype=np.float64),
+            "Ea": np.ascontiguousarray(mech["Ea"], dtype=np.float64),
+            "rev": np.ascontiguousarray(mech["reversible"], dtype=np.uint8),
+        }
+        k = self._keep
+        self.c = _Mech(int(mech["n_s"]), int(mech["n_r"]),
+                       *[k[f].ctypes.data for f in ("W", "nasa_lo", "nasa_hi", "T_mid",
+                                                    "rxn_ptr", "sp_idx", "nu", "order",
+                                                    "A", "b", "Ea", "rev")])
+        self.n_s = int(mech["n_s"])
+        self.n_r = int(mech["n_r"])
+
+
+def make_params(**kw):
+    d = dict(DEFAULT_PARAMS)
+    d.update(kw)
+    return _Params(d["ystep_max"], d["delta_max"], d["alpha"], d["tol_ring"], d["tol_freq"],
+                   d["r_fac"], d["rof_min"], int(d["dft_window"]), 0, int(d["max_iters"]))
+
+
+def thermo(om, k, T):
+    out = np.zeros(3)
+    lib().orc_thermo(C.byref(om.c), int(k), float(T), _p(out))
+    return out
+
+
+def ystarstar(y, alpha):
+    return lib().orc_ystarstar(float(y), float(alpha))
+
+
+def source(om, T, P, Y, rOF=None, **kw):
+    """Returns dict(q, omega, dYdt, dTdt, rho) for one state."""
+    prm = make_params(**kw)
+    Y = np.ascontiguousarray(Y, dtype=np.float64)
+    rOF = np.ones(om.n_r) if rOF is None else np.ascontiguousarray(rOF, dtype=np.float64)
+    q = np.zeros(om.n_r)
+    om_ = np.zeros(om.n_s)
+    dY = np.zeros(om.n_s)
+    dT = np.zeros(1)
+    rho = np.zeros(1)
+    lib().orc_source(C.byref(om.c), C.byref(prm), float(T), float(P), _p(Y), _p(rOF), _p(q),
+                     _p(om_), _p(dY), _p(dT), _p(rho))
+    return dict(q=q, omega=om_, dYdt=dY, dTdt=float(dT[0]), rho=float(rho[0]))
+
+
+def step_size(Y, dYdt, t, tf, **kw):
+    prm = make_params(**kw)
+    Y = np.ascontiguousarray(Y, dtype=np.float64)
+    dYdt = np.ascontiguousarray(dYdt, dtype=np.float64)
+    return lib().orc_step_size(C.byref(prm), len(Y), _p(Y), _p(dYdt), float(t), float(tf))
+
+
+def dft_mag(x):
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    D = np.zeros(len(x))
+    lib().orc_dft_mag(_p(x), len(x), _p(D))
+    return D
+
+
+def ringing_eq(D, **kw):
+    prm = make_params(**kw)
+    D = np.ascontiguousarray(D, dtype=np.float64)
+    mg = np.zeros(1)
+    r = lib().orc_ringing_eq(_p(D), len(D), C.byref(prm), _p(mg))
+    return bool(r), float(mg[0])
+
+
+def rof_next(rof, ring_eq, **kw):
+    prm = make_params(**kw)
+    return lib().orc_rof_next(float(rof), int(bool(ring_eq)), C.byref(prm))
+
+
+def integrate_cell(om, T, P, Y, tf, trace_cap=0, **kw):
+    prm = make_params(**kw)
+    Tb = np.array([float(T)])
+    Yb = np.array(Y, dtype=np.float64).copy()
+    it = C.c_longlong(0)
+    md = np.zeros(1)
+    my = np.zeros(1)
+    tr = np.zeros(max(trace_cap, 1))
+    st = lib().orc_integrate_cell(C.byref(om.c), C.byref(prm), _p(Tb), float(P), _p(Yb),
+                                  float(tf), C.byref(it), _p(md), _p(my),
+                                  _p(tr) if trace_cap else None, int(trace_cap))
+    out = dict(T=float(Tb[0]), Y=Yb, iters=int(it.value), status=int(st),
+               margin_dft=float(md[0]), margin_y=float(my[0]))
+    if trace_cap:
+        out["h"] = tr[:min(trace_cap, it.value)]
+    return out
+
+
+def integrate(om, T, P, Y, tf, nthreads=0, **kw):
+    """Integrate all cells; returns dict(T, Y, iters, status, margin_dft, margin_y)."""
+    prm = make_params(**kw)
+    T = np.array(T, dtype=np.float64).copy()
+    P = np.ascontiguousarray(P, dtype=np.float64)
+    Y = np.array(Y, dtype=np.float64).copy()
+    n = len(T)
+    iters = np.zeros(n, dtype=np.int64)
+    status = np.zeros(n, dtype=np.uint8)
+    md = np.zeros(n)
+    my = np.zeros(n)
+    lib().orc_integrate(C.byref(om.c), C.byref(prm), n, _p(T), _p(P), _p(Y), Y.shape[1],
+                        float(tf), iters.ctypes.data_as(C.POINTER(C.c_longlong)),
+                        status.ctypes.data_as(C.POINTER(C.c_ubyte)), _p(md), _p(my),
+                        int(nthreads))
+    return dict(T=T, Y=Y, iters=iters, status=status, margin_dft=md, margin_y=my)
+
+
+def nasa_targets(om, T):
+    T = np.ascontiguousarray(T, dtype=np.float64)
+    cp = np.zeros((len(T), om.n_s))
+    h = np.zeros((len(T), om.n_s))
+    lib().orc_nasa_targets(C.byref(om.c), len(T), _p(T), _p(cp), _p(h))
+    return cp, h
+
+
+def mlp_n_params(H, n_out):
+    return int(lib().orc_mlp_n_params(H, n_out))
+
+
+def mlp_forward(H, n_out, prm, x):
+    prm = np.ascontiguousarray(prm, dtype=np.float64)
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    y = np.zeros((len(x), n_out))
+    lib().orc_mlp_forward(H, n_out, _p(prm), len(x), _p(x), _p(y))
+    return y
+
+
+def mlp_loss_grad(H, n_out, prm, x, target):
+    prm = np.ascontiguousarray(prm, dtype=np.float64)
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    t = np.ascontiguousarray(target, dtype=np.float64)
+    g = np.zeros_like(prm)
+    loss = lib().orc_mlp_loss_grad(H, n_out, _p(prm), len(x), _p(x), _p(t), _p(g))
+    return loss, g
+
+
+def adam_step(prm, grad, m1, m2, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+    """In-place Adam update of prm, m1, m2 (float64 arrays)."""
+    lib().orc_adam_step(len(prm), _p(prm), _p(np.ascontiguousarray(grad)), _p(m1), _p(m2),
+                        int(step), lr, beta1, beta2, eps)

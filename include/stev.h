@@ -1,0 +1,212 @@
+/*
+ * libstev -- STEV stiff-chemistry integrator for one AMD Instinct MI355X
+ * (gfx950).  C ABI: plain pointers and sizes only.
+ *
+ * Method: Buchheit et al., "STEV: A Stabilized Explicit Variable-Load Solver
+ * with Machine Learning Acceleration for the Rapid Solution of Stiff Chemical
+ * Kinetics", arXiv:1905.09395.  Each cell of a CFD field is advanced over one
+ * flow time step dt_flow (operator splitting, Sec 5) by forward Euler
+ * (Sec 4, Eq 18) with its own step size (Sec 2.1, Eqs 1-5), small-species
+ * stabilisation (Sec 2.2, Eqs 6-7), DFT ringing damping of reversible rates
+ * (Sec 2.3, Eqs 8-14) and variable loading (Sec 2.4): finished cells leave
+ * the work set and free lanes are refilled with new cells.
+ *
+ * Units: T [K], P [Pa], Y mass fractions; W [kg/mol]; A in cm-mol-s as in
+ * Table 1 (converted per reaction by its forward order); Ea [J/mol].
+ *
+ * Return codes: every entry point returns one of the STEV_* codes below and
+ * records a message retrievable with stev_last_error() (per context).  On
+ * STEV_EINVAL no caller memory has been touched.
+ */
+#ifndef STEV_H
+#define STEV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define STEV_OK 0
+#define STEV_EINVAL 1    /* bad argument; nothing was touched */
+#define STEV_ENOMEM 2    /* request can never fit the HBM budget / alloc failed */
+#define STEV_EAGAIN 3    /* submitted request still running */
+#define STEV_ENOTFOUND 4 /* unknown ticket */
+#define STEV_EDEVICE 5   /* HIP runtime error */
+#define STEV_ECELLS 6    /* some cells failed: see status_out (1 non-finite, 2 max_iters) */
+
+#define STEV_F64 0       /* T, P, Y are double*   */
+#define STEV_F32 1       /* T, P, Y are float*    */
+#define STEV_THERMO_POLY 0 /* NASA-7 polynomials (Eqs 15-16)            */
+#define STEV_THERMO_MLP 1  /* trained network for cp and h (Sec 3)       */
+
+typedef struct stev_ctx stev_ctx;
+typedef struct stev_mech stev_mech;
+
+/* Mechanism description (Sec 7.1 forms: Eqs 26-30).  Plain host data; the
+ * library copies it in stev_create_mechanism and the caller keeps ownership.
+ * Reaction j's participants are entries rxn_ptr[j] .. rxn_ptr[j+1]-1 of
+ * sp_idx / nu / order.  nu < 0 marks a reactant (order = forward order),
+ * nu > 0 a product (order = reverse order, used only if reversible[j]). */
+typedef struct {
+  int32_t n_species;
+  int32_t n_reactions;
+  const double *W;          /* [n_species] molar mass, kg/mol (> 0) */
+  const double *nasa_lo;    /* [n_species][7] a1..a7 used for T <  T_mid */
+  const double *nasa_hi;    /* [n_species][7] a1..a7 used for T >= T_mid */
+  const double *T_mid;      /* [n_species] K */
+  const int32_t *rxn_ptr;   /* [n_reactions+1], rxn_ptr[0] = 0 */
+  const int32_t *sp_idx;    /* [nnz] species index in [0, n_species) */
+  const double *nu;         /* [nnz] signed net stoichiometric coefficient (!= 0) */
+  const double *order;      /* [nnz] rate order (>= 0) */
+  const double *A;          /* [n_reactions] pre-exponential, cm-mol-s */
+  const double *b;          /* [n_reactions] temperature exponent */
+  const double *Ea;         /* [n_reactions] activation energy, J/mol */
+  const uint8_t *reversible;/* [n_reactions] 0/1 */
+} stev_mech_desc;
+
+/* Solver parameters.  stev_default_params() fills the defaults below. */
+typedef struct {
+  int32_t precision;      /* STEV_F64 | STEV_F32 */
+  int32_t thermo;         /* STEV_THERMO_POLY | STEV_THERMO_MLP */
+  double ystep_max;       /* Eq 3 max species consumption per step  (1e-3) */
+  double delta_max;       /* Eq 4 max step fraction of dt_flow      (1e-2) */
+  double alpha;           /* Eq 7 species limit factor              (1e-5) */
+  double tol_ring;        /* Eq 12 ringing tolerance                (0.5)  */
+  double tol_freq;        /* Eq 12 equilibrium tolerance, mol/m^3   (1e-6) */
+  double r_fac;           /* Eq 12 damping factor, > 1              (2.0)  */
+  double rof_min;         /* floor of rOF, > 0                      (1e-12) */
+  int32_t dft_window;     /* Eq 8 ring length: 13, or 0 to disable  (13)   */
+  int32_t lanes_per_cell; /* 0 auto, else 1|8|16|32|64                      */
+  int64_t max_iters;      /* per-cell iteration cap -> status 2     (1e6)  */
+  int32_t waves_per_wg;   /* 0 auto (1..16)                                  */
+  int32_t compact_every;  /* refill cadence K in iterations, 0 auto (1)     */
+  int32_t grid_wgs;       /* persistent workgroups, 0 auto                  */
+  int32_t reserved;
+} stev_params;
+
+/* Per-call statistics. */
+typedef struct {
+  int64_t n_cells;
+  int64_t total_iters;    /* sum over cells of iterations */
+  int64_t max_cell_iters;
+  int64_t n_failed;       /* cells with status != 0 */
+  double kernel_ms;       /* HIP-event time of the integration launch(es) */
+  double total_ms;        /* wall time inside the call (incl. copies) */
+  int32_t lanes_per_cell; /* variant actually used */
+  int32_t waves_per_wg;
+  int32_t grid_wgs;
+  int32_t compact_every;
+  double latency_ms;      /* serving: submit -> completion observed */
+} stev_stats;
+
+void stev_default_params(stev_params *p);
+
+/* Open a context on HIP device `hip_device`.  hbm_budget_bytes bounds the
+ * device memory the context may hold for work buffers (0 = 90% of free). */
+int stev_init(stev_ctx **ctx, int hip_device, size_t hbm_budget_bytes);
+
+/* Use this HIP stream (hipStream_t passed as void*) for subsequent
+ * stev_integrate calls; NULL selects the context's own stream. */
+int stev_set_stream(stev_ctx *ctx, void *hip_stream);
+
+/* Copy, validate and pack a mechanism; device-resident until destroyed.
+ * Errors: STEV_EINVAL for out-of-range indices, nu == 0, W <= 0, more than
+ * 6 participants in a reaction, or sizes beyond the compiled variants
+ * (n_species <= 64, n_reactions <= 384). */
+int stev_create_mechanism(stev_ctx *ctx, const stev_mech_desc *desc, stev_mech **out);
+
+/* Integrate n_cells cells over one flow step dt_flow, in place (Sec 2.4).
+ * T[c], P[c]: per-cell temperature and pressure; Y[c*ld_cell + k*ld_species]
+ * mass fraction of species k.  T, P, Y may be host or device pointers (any
+ * mix), typed double or float per params->precision.  P is read-only.
+ * iters_out (int32[n_cells]) and status_out (uint8[n_cells]) are optional,
+ * host or device.  Blocking: returns when results are written.  A failed
+ * cell keeps its last finite state.  Returns STEV_ECELLS if any cell has a
+ * non-zero status.  params may be NULL (defaults). */
+int stev_integrate(stev_ctx *ctx, const stev_mech *mech, int64_t n_cells,
+                   void *T, const void *P, void *Y, int64_t ld_cell,
+                   int64_t ld_species, double dt_flow, const stev_params *params,
+                   int32_t *iters_out, uint8_t *status_out, stev_stats *stats);
+
+/* Many independent cell batches (possibly different mechanisms) in one
+ * persistent launch per mechanism group.  Arrays of length n_batches; every
+ * batch uses `params` (its precision selects the pointer types).  Device
+ * pointers only.  iters_out/status_out entries may be NULL. */
+int stev_integrate_batched(stev_ctx *ctx, int32_t n_batches, const stev_mech *const *mechs,
+                           const int64_t *n_cells, void *const *T, const void *const *P,
+                           void *const *Y, const int64_t *ld_cell, const int64_t *ld_species,
+                           double dt_flow, const stev_params *params,
+                           int32_t *const *iters_out, uint8_t *const *status_out,
+                           stev_stats *stats);
+
+/* Serving: enqueue one solve; returns at once with a ticket.  Device
+ * pointers only; arrays must stay valid and untouched until stev_poll
+ * returns STEV_OK.  Admission is by the HBM budget: a request whose work
+ * buffers can never fit returns STEV_ENOMEM; one that does not fit now is
+ * queued.  Thread-safe with respect to stev_poll. */
+int stev_submit(stev_ctx *ctx, const stev_mech *mech, int64_t n_cells, void *T,
+                const void *P, void *Y, int64_t ld_cell, int64_t ld_species,
+                double dt_flow, const stev_params *params, int32_t *iters_out,
+                uint8_t *status_out, uint64_t *ticket);
+
+/* STEV_OK when done (stats filled; the ticket is then released),
+ * STEV_EAGAIN while pending, STEV_ENOTFOUND for an unknown ticket,
+ * STEV_ECELLS when done with failed cells. */
+int stev_poll(stev_ctx *ctx, uint64_t ticket, stev_stats *stats);
+
+/* Thermo network (Sec 3): train 1 -> H tanh -> H tanh -> 2 n_species
+ * (cp/R and h/R, z-scored) on GPU-sampled NASA-7 targets with the library's
+ * own forward/backward/Adam kernels, then attach BF16 weights to `mech` for
+ * STEV_THERMO_MLP.  Range [T_lo, T_hi]; outside it the kernel falls back to
+ * the polynomials. */
+typedef struct {
+  int32_t hidden;          /* 32 */
+  int32_t epochs;          /* passes over the samples */
+  int64_t n_samples;       /* 1 << 20 */
+  int32_t batch;           /* minibatch size */
+  int32_t seed;
+  double lr;               /* Adam learning rate */
+  double T_lo, T_hi;       /* trained range, K (300, 3000) */
+  double holdout_frac;     /* 1/8 */
+} stev_mlp_cfg;
+
+typedef struct {
+  double train_loss, test_loss;       /* z-scored MSE */
+  double max_rel_err_cp, mean_rel_err_cp;
+  double max_rel_err_h, mean_rel_err_h;   /* relative to max |h/R| per species */
+  double train_ms;
+  int64_t steps;
+} stev_mlp_report;
+
+int stev_train_thermo_mlp(stev_ctx *ctx, stev_mech *mech, const stev_mlp_cfg *cfg,
+                          stev_mlp_report *report);
+
+/* Export / import the FP32 master weights of an attached network
+ * (layout W1[H] b1[H] W2[H][H] b2[H] W3[2n][H] b3[2n], then 4n z-score
+ * constants mean_cp[n] std_cp[n] mean_h[n] std_h[n]).  n_values in/out. */
+int stev_get_thermo_mlp(stev_ctx *ctx, const stev_mech *mech, float *values, int64_t *n_values);
+int stev_set_thermo_mlp(stev_ctx *ctx, stev_mech *mech, int32_t hidden, double T_lo,
+                        double T_hi, const float *values, int64_t n_values);
+
+/* Pick lanes_per_cell, waves_per_wg and compact_every by timing trial runs
+ * on a private copy of up to n_cells_hint synthetic cells drawn from the
+ * given device state (read-only).  Results are written to *inout and cached
+ * per (mechanism shape, precision, thermo, size bucket). */
+int stev_autotune(stev_ctx *ctx, const stev_mech *mech, int64_t n_cells, const void *T,
+                  const void *P, const void *Y, int64_t ld_cell, int64_t ld_species,
+                  double dt_flow, stev_params *inout);
+
+/* Model FLOPs of one cell-iteration for this mechanism (add/mul = 1,
+ * FMA = 2; transcendentals counted separately in *transc). */
+double stev_model_flops(const stev_mech *mech, int32_t thermo, double *transc);
+
+void stev_destroy_mechanism(stev_ctx *ctx, stev_mech *mech);
+void stev_shutdown(stev_ctx *ctx);
+const char *stev_last_error(const stev_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

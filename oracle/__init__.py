@@ -45,12 +45,13 @@ class _Params(C.Structure):
                 ("alpha", C.c_double), ("tol_ring", C.c_double),
                 ("tol_freq", C.c_double), ("r_fac", C.c_double),
                 ("rof_min", C.c_double), ("dft_window", C.c_int), ("pad_", C.c_int),
-                ("max_iters", C.c_longlong)]
+                ("max_iters", C.c_longlong), ("noise_eps", C.c_double),
+                ("noise_seed", C.c_ulonglong)]
 
 
 DEFAULT_PARAMS = dict(ystep_max=1e-3, delta_max=1e-2, alpha=1e-5, tol_ring=0.5,
                       tol_freq=1e-6, r_fac=2.0, rof_min=1e-12, dft_window=13,
-                      max_iters=1_000_000)
+                      max_iters=1_000_000, noise_eps=0.0, noise_seed=0)
 
 
 def lib():
@@ -128,7 +129,8 @@ def make_params(**kw):
     d = dict(DEFAULT_PARAMS)
     d.update(kw)
     return _Params(d["ystep_max"], d["delta_max"], d["alpha"], d["tol_ring"], d["tol_freq"],
-                   d["r_fac"], d["rof_min"], int(d["dft_window"]), 0, int(d["max_iters"]))
+                   d["r_fac"], d["rof_min"], int(d["dft_window"]), 0, int(d["max_iters"]),
+                   float(d["noise_eps"]), int(d["noise_seed"]))
 
 
 def thermo(om, k, T):

@@ -68,9 +68,28 @@ double orc_ystarstar(double y, double alpha) {
  *   dT/dt = -sum_k H_k omega_k / (rho cp)   (isobaric, adiabatic)
  * q receives the undamped net rates.
  * ------------------------------------------------------------------------- */
+/* splitmix64 (Steele, Lea & Flood 2014), used only by the noise instrument */
+static unsigned long long orc_mix64(unsigned long long z) {
+  z += 0x9E3779B97F4A7C15ULL;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+  return z ^ (z >> 31);
+}
+
+static double orc_noise_u(unsigned long long key, int j) {
+  unsigned long long r = orc_mix64(key ^ orc_mix64(0x51ED27ULL + (unsigned long long)j));
+  return (double)(r >> 11) * (1.0 / 4503599627370496.0) - 1.0;   /* [-1, 1) */
+}
+
 void orc_source(const orc_mech *m, const orc_params *p, double T, double P,
                 const double *Y, const double *rOF, double *q, double *omega,
                 double *dYdt, double *dTdt, double *rho_out) {
+  orc_source_keyed(m, p, T, P, Y, rOF, q, omega, dYdt, dTdt, rho_out, 0ULL);
+}
+
+void orc_source_keyed(const orc_mech *m, const orc_params *p, double T, double P,
+                      const double *Y, const double *rOF, double *q, double *omega,
+                      double *dYdt, double *dTdt, double *rho_out, unsigned long long key) {
   int n_s = m->n_s, n_r = m->n_r;
   double *cp_R = (double *)malloc(sizeof(double) * 4 * (size_t)n_s);
   double *h_RT = cp_R + n_s;
@@ -104,6 +123,7 @@ void orc_source(const orc_mech *m, const orc_params *p, double T, double P,
     for (int i = p0; i < p1; ++i)
       if (m->nu[i] < 0.0) prod_f *= pow(C[m->sp_idx[i]], m->order[i]);
     double qj = kf * prod_f;
+    double gross = fabs(qj);
     if (m->rev[j]) {
       double dG_RT = 0.0, dN = 0.0;
       for (int i = p0; i < p1; ++i) {
@@ -116,7 +136,9 @@ void orc_source(const orc_mech *m, const orc_params *p, double T, double P,
       for (int i = p0; i < p1; ++i)
         if (m->nu[i] > 0.0) prod_r *= pow(C[m->sp_idx[i]], m->order[i]);
       qj = qj - kr * prod_r;
+      if (fabs(kr * prod_r) > gross) gross = fabs(kr * prod_r);
     }
+    if (p->noise_eps > 0.0) qj += p->noise_eps * gross * orc_noise_u(key, j);
     q[j] = qj;
     double qeff = m->rev[j] ? rOF[j] * qj : qj;
     for (int i = p0; i < p1; ++i) omega[m->sp_idx[i]] += m->nu[i] * qeff;
@@ -200,6 +222,14 @@ int orc_integrate_cell(const orc_mech *m, const orc_params *p, double *T_io,
                        double P, double *Y_io, double tf, long long *iters,
                        double *margin_dft, double *margin_y,
                        double *h_trace, long long trace_cap) {
+  return orc_integrate_cell_keyed(m, p, T_io, P, Y_io, tf, iters, margin_dft, margin_y,
+                                  h_trace, trace_cap, 0);
+}
+
+int orc_integrate_cell_keyed(const orc_mech *m, const orc_params *p, double *T_io,
+                             double P, double *Y_io, double tf, long long *iters,
+                             double *margin_dft, double *margin_y,
+                             double *h_trace, long long trace_cap, long long cell) {
   int n_s = m->n_s, n_r = m->n_r, W = p->dft_window;
   size_t nd = (size_t)(4 * n_s + 2 * n_r + (W > 0 ? n_r * W + W : 0));
   double *buf = (double *)calloc(nd, sizeof(double));
@@ -218,7 +248,9 @@ int orc_integrate_cell(const orc_mech *m, const orc_params *p, double *T_io,
   while (t < tf) {
     if (it >= p->max_iters) { status = 2; break; }
     double dTdt, rho;
-    orc_source(m, p, T, P, Y, rOF, q, omega, dYdt, &dTdt, &rho);
+    unsigned long long key = p->noise_seed ^ orc_mix64((unsigned long long)cell * 0x100000001ULL +
+                                                       (unsigned long long)it);
+    orc_source_keyed(m, p, T, P, Y, rOF, q, omega, dYdt, &dTdt, &rho, key);
     for (int k = 0; k < n_s; ++k) {
       double d = fabs(Y[k] - 1.0e-20) / 1.0e-20;
       if (d < my) my = d;
@@ -271,8 +303,8 @@ int orc_integrate(const orc_mech *m, const orc_params *p, long long n,
   for (long long c = 0; c < n; ++c) {
     long long it = 0;
     double md = 0.0, my = 0.0;
-    int st = orc_integrate_cell(m, p, &T[c], P[c], &Y[c * ld], tf, &it, &md,
-                                &my, NULL, 0);
+    int st = orc_integrate_cell_keyed(m, p, &T[c], P[c], &Y[c * ld], tf, &it, &md,
+                                      &my, NULL, 0, c);
     if (iters) iters[c] = it;
     if (status) status[c] = (unsigned char)st;
     if (margin_dft) margin_dft[c] = md;

@@ -47,6 +47,12 @@ typedef struct {
   int dft_window;     /* Eq 8 ring length; 0 disables the DFT stabilisation */
   int pad_;
   long long max_iters;
+  /* Test instrument, not part of the method: when noise_eps > 0 every net
+   * rate gets + noise_eps * max(q_f, q_r) * u, u uniform in [-1, 1) from a
+   * counter-based hash of (noise_seed, cell, iteration, reaction).  Ensembles
+   * of such runs show how far rounding at a given precision can move a cell. */
+  double noise_eps;
+  unsigned long long noise_seed;
 } orc_params;
 
 /* Eq 15, Eq 16 and the standard NASA-7 entropy: out = {cp/R, h/RT, s/R}. */
@@ -59,6 +65,10 @@ double orc_ystarstar(double y, double alpha);
 void orc_source(const orc_mech *m, const orc_params *p, double T, double P,
                 const double *Y, const double *rOF, double *q, double *omega,
                 double *dYdt, double *dTdt, double *rho);
+/* Same, with the noise instrument keyed by (cell, iteration). */
+void orc_source_keyed(const orc_mech *m, const orc_params *p, double T, double P,
+                      const double *Y, const double *rOF, double *q, double *omega,
+                      double *dYdt, double *dTdt, double *rho, unsigned long long key);
 
 /* Eqs 1-5 plus the clamp to the end of the flow step. */
 double orc_step_size(const orc_params *p, int n_s, const double *Y,
@@ -80,6 +90,11 @@ int orc_integrate_cell(const orc_mech *m, const orc_params *p, double *T,
                        double P, double *Y, double tf, long long *iters,
                        double *margin_dft, double *margin_y,
                        double *h_trace, long long trace_cap);
+/* Same; `cell` only keys the noise instrument. */
+int orc_integrate_cell_keyed(const orc_mech *m, const orc_params *p, double *T,
+                             double P, double *Y, double tf, long long *iters,
+                             double *margin_dft, double *margin_y,
+                             double *h_trace, long long trace_cap, long long cell);
 
 /* All cells; Y row-major with leading dimension ld (>= n_s).  Optional
  * outputs may be NULL.  nthreads <= 0 uses the OpenMP default. */

@@ -1,0 +1,98 @@
+// Internal layout shared by the STEV kernels and the host runtime.
+//
+// The packed mechanism ("blob") is one contiguous device buffer that every
+// workgroup stages into LDS once per launch.  All floating-point entries are
+// of the kernel's compute type R (double or float); index entries are int32.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace stev {
+
+constexpr int kWin = 13;       // DFT ring length (Sec 2.3: thirteen most recent values)
+constexpr int kMaxPart = 6;    // participants per reaction (reactants + products)
+constexpr int kMaxSpecies = 64;
+constexpr int kMaxReactions = 384;
+
+// --- species block: kSpStride values of R per species ------------------------
+// [SP_TMID] T_mid, [SP_W] W, [SP_INVW] 1/W, then two coefficient sets of
+// kSetLen values (low set at SP_LO, high set at SP_HI):
+//   a1 | a2..a5 (cp/R) | a2/2..a5/5 (h/RT) | a6 | -a2/2,-a3/6,-a4/12,-a5/20
+//   (g = h/RT - s/R) | a2, a3/2, a4/3, a5/4 (s/R) | a7
+constexpr int SP_TMID = 0, SP_W = 1, SP_INVW = 2, SP_LO = 4;
+constexpr int kSetLen = 19;
+constexpr int SP_HI = SP_LO + kSetLen;
+constexpr int kSpStride = 42;
+constexpr int C_A1 = 0, C_CP = 1, C_H = 5, C_A6 = 9, C_G = 10, C_S = 14, C_A7 = 18;
+
+// --- reaction block: kRxStride values of R per reaction ------------------------
+// Rate-law factors sit in fixed slots: 0..2 forward (reactants), 3..5 reverse
+// (products).  An integer order n of a species fills n slots with order 1;
+// other orders take one slot with their exponent; empty slots point at the
+// unit entry of the concentration table.
+//   ln A_SI, b, Ea/R, dN, T_mid of the participants, pad,
+//   order[6], then the reaction's Gibbs coefficient sets (low, high):
+//   sum nu a1 | sum nu (-a2/2, -a3/6, -a4/12, -a5/20) | sum nu a6 | sum nu a7
+//   so that dG/RT = d1 (1 - ln T) + T (d2 + T (d3 + T (d4 + T d5))) + d6/T - d7,
+//   then nu[6] (used only when participants do not share one T_mid).
+constexpr int kHalfPart = 3;
+constexpr int RX_LNA = 0, RX_B = 1, RX_TH = 2, RX_DN = 3, RX_TMID = 4;
+constexpr int RX_ORD = 6, RX_DLO = 12, RX_DHI = 19, RX_NU = 26;
+constexpr int kRxStride = 32;
+
+// Offsets (bytes) of each array inside a mechanism blob.  Every table has one
+// extra "dummy" row (species n_s, reaction n_r) so that lanes past the end of
+// the mechanism read valid, harmless data instead of branching around it:
+// the dummy species has zero coefficients and no reactions; the dummy
+// reaction has ln A = -inf (k_f = 0) and all slots on the unit entry.
+struct MechLayout {
+  int n_s, n_r, n_rev, nnz_csr;
+  int has_frac;        // a slot carries an order other than 1 (pow needed)
+  int mixed_tmid;      // some reaction's participants differ in T_mid
+  int dmax;            // padded species -> reaction CSR width
+  int bytes;           // total blob size (multiple of 16)
+  int off_sp;          // R   [n_s+1][kSpStride]
+  int off_rx;          // R   [n_r+1][kRxStride]
+  int off_rxi;         // i32 [n_r+1][kMaxPart] slot species: n_s = unit entry
+  int off_cj;          // i32 [n_s+1][dmax]     reaction (packed order); n_r = zero entry
+  int off_cnu;         // R   [n_s+1][dmax]     nu (0 on padding)
+};
+
+// Thermo network attached to a mechanism (Sec 3): 1 -> H -> H -> 2 n_s.
+struct MlpDev {
+  int enabled, hidden;
+  float T_lo, T_hi, x_scale, x_shift;   // x = (T - x_shift) * x_scale
+  const float *w1, *b1;                 // [H]
+  const float *b2;                      // [H]
+  const uint16_t *w2hi, *w2lo;          // bf16 [H][H]  (row = output unit)
+  const float *b3;                      // [2 n_s]
+  const uint16_t *w3hi, *w3lo;          // bf16 [2 n_s padded to 64][H]
+  const float *out_mean, *out_std;      // [2 n_s]: cp/R then h/R
+};
+
+struct KArgs {
+  const void *blob;
+  MechLayout L;
+  int wave_bytes;          // per-wave LDS scratch
+  int lds_mech_bytes;      // blob bytes staged (aligned)
+  // cells
+  long long n_cells;
+  void *T;
+  const void *P;
+  void *Y;
+  long long ld_cell, ld_sp;
+  int *iters_out;          // device, nullable
+  unsigned char *status_out;
+  // parameters
+  double tf, dtmax;
+  double ystep, alpha, tol_ring2, tol_freq, r_fac, r_fac_inv, rof_min;
+  double ln_patm_r;        // ln(P_atm / R)
+  long long max_iters;
+  int dft_on, compact_every;
+  // control: [0] next cell, [1] sum iters, [2] max iters, [3] failed cells
+  unsigned long long *ctl;
+  MlpDev mlp;
+};
+
+}  // namespace stev

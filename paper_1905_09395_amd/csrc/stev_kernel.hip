@@ -1,0 +1,548 @@
+// Persistent STEV kernel for gfx950 (CDNA4).
+//
+// One wavefront carries 64/G cells; a cell is owned by a group of G lanes.
+// Lane l of a group handles species k = l + s*G (s < SPL) and reactions
+// j = l + r*G (r < RPL; reversible reactions are packed first so only
+// r < RRPL ever carries a DFT ring).  Effective concentrations (and, for
+// mechanisms whose reactions mix NASA-7 break temperatures, Gibbs terms) go
+// from species lanes to reaction lanes, and damped net rates come back,
+// through a small per-wave LDS area; group sums and minima use DPP row
+// operations and the gfx950 permlane swaps.  The packed mechanism is staged
+// into LDS once per workgroup.
+//
+// Per cell and iteration (Sec 2, Sec 4):
+//   thermo (Eqs 15-16) -> mixture density and gamma-concentrations (Eqs 6-7)
+//   -> k_f, K from the reaction's Gibbs polynomial (Eqs 28-30), damped by rOF
+//   (Eq 14) -> omega = nu^T q_eff, dY/dt, dT/dt -> step size (Eqs 1-5,
+//   clamped to the flow step) -> forward Euler (Eq 18) -> ring of q h (Eq 8),
+//   |DFT| at bins 0 and 4..6 (Eqs 9-10) -> rOF update (Eqs 11-13).
+// Variable loading (Sec 2.4): when a cell reaches t_f its state is written
+// back and the group takes the next cell index from a global counter; the
+// wave claims all new cells with one atomic and hands them out by ballot
+// rank.  A wave exits when the counter is exhausted and its groups are idle.
+#include "stev_internal.h"
+
+namespace stev {
+
+constexpr double kRgas = 8.31446261815324;   // J/(mol K)
+
+// cos and sin of 2 pi r / 13 for r = 0..6, rounded to double from a 40-digit
+// evaluation.  X_k = x_0 + sum_{m=1..6} (x_m + x_{13-m}) cos(2 pi k m / 13)
+//                  - i (x_m - x_{13-m}) sin(2 pi k m / 13).
+constexpr double kCos13[7] = {1.0, 0.8854560256532099, 0.5680647467311558,
+                              0.12053668025532305, -0.3546048870425356,
+                              -0.7485107481711011, -0.970941817426052};
+constexpr double kSin13[7] = {0.0, 0.46472317204376856, 0.8229838658936564,
+                              0.992708874098054, 0.9350162426854148,
+                              0.6631226582407952, 0.23931566428755777};
+// coefficient of (x_m + x_{13-m}) in Re X_k
+__host__ __device__ constexpr double tw_re(int k, int m) {
+  return ((k * m) % 13) <= 6 ? kCos13[(k * m) % 13] : kCos13[13 - (k * m) % 13];
+}
+// coefficient of (x_m - x_{13-m}) in Im X_k (= -sin(2 pi k m / 13))
+__host__ __device__ constexpr double tw_im(int k, int m) {
+  return ((k * m) % 13) <= 6 ? -kSin13[(k * m) % 13] : kSin13[13 - (k * m) % 13];
+}
+
+__device__ __forceinline__ void wave_lds_sync() {
+  // LDS traffic of one wavefront is processed in order; this only keeps the
+  // compiler from moving LDS accesses across the exchange points.
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// ---- cross-lane exchange -----------------------------------------------------
+// Symmetric partner exchanges: each step pairs lanes two by two, so an
+// all-reduce built from them leaves bit-identical results in every lane of a
+// group (the combining operations used here are commutative).
+template <int CTRL>
+__device__ __forceinline__ int dpp_i(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xf, 0xf, false);
+}
+__device__ __forceinline__ int swap16_i(int v) {   // partner lane ^ 16
+  auto p = __builtin_amdgcn_permlane16_swap((unsigned)v, (unsigned)v, false, false);
+  return ((threadIdx.x >> 4) & 1) ? (int)p[0] : (int)p[1];
+}
+__device__ __forceinline__ int swap32_i(int v) {   // partner lane ^ 32
+  auto p = __builtin_amdgcn_permlane32_swap((unsigned)v, (unsigned)v, false, false);
+  return ((threadIdx.x >> 5) & 1) ? (int)p[0] : (int)p[1];
+}
+
+template <int STEP>
+__device__ __forceinline__ int xchg(int v) {
+  if constexpr (STEP == 1) return dpp_i<0xB1>(v);        // quad_perm [1,0,3,2]
+  else if constexpr (STEP == 2) return dpp_i<0x4E>(v);   // quad_perm [2,3,0,1]
+  else if constexpr (STEP == 4) return dpp_i<0x141>(v);  // row_half_mirror
+  else if constexpr (STEP == 8) return dpp_i<0x140>(v);  // row_mirror
+  else if constexpr (STEP == 16) return swap16_i(v);
+  else return swap32_i(v);
+}
+template <int STEP>
+__device__ __forceinline__ float xchg(float v) {
+  return __int_as_float(xchg<STEP>(__float_as_int(v)));
+}
+template <int STEP>
+__device__ __forceinline__ double xchg(double v) {
+  const int lo = xchg<STEP>(__double2loint(v));
+  const int hi = xchg<STEP>(__double2hiint(v));
+  return __hiloint2double(hi, lo);
+}
+
+template <int G, typename V>
+__device__ __forceinline__ V grp_sum(V v) {
+  if constexpr (G >= 2) v += xchg<1>(v);
+  if constexpr (G >= 4) v += xchg<2>(v);
+  if constexpr (G >= 8) v += xchg<4>(v);
+  if constexpr (G >= 16) v += xchg<8>(v);
+  if constexpr (G >= 32) v += xchg<16>(v);
+  if constexpr (G >= 64) v += xchg<32>(v);
+  return v;
+}
+template <int G, typename V>
+__device__ __forceinline__ V grp_min(V v) {
+  if constexpr (G >= 2) v = fmin(v, xchg<1>(v));
+  if constexpr (G >= 4) v = fmin(v, xchg<2>(v));
+  if constexpr (G >= 8) v = fmin(v, xchg<4>(v));
+  if constexpr (G >= 16) v = fmin(v, xchg<8>(v));
+  if constexpr (G >= 32) v = fmin(v, xchg<16>(v));
+  if constexpr (G >= 64) v = fmin(v, xchg<32>(v));
+  return v;
+}
+template <int G>
+__device__ __forceinline__ int grp_or(int v) {
+  if constexpr (G >= 2) v |= xchg<1>(v);
+  if constexpr (G >= 4) v |= xchg<2>(v);
+  if constexpr (G >= 8) v |= xchg<4>(v);
+  if constexpr (G >= 16) v |= xchg<8>(v);
+  if constexpr (G >= 32) v |= xchg<16>(v);
+  if constexpr (G >= 64) v |= xchg<32>(v);
+  return v;
+}
+
+template <typename R> struct Math;
+template <> struct Math<double> {
+  static __device__ __forceinline__ double ex(double x) { return exp(x); }
+  static __device__ __forceinline__ double lg(double x) { return log(x); }
+  static __device__ __forceinline__ bool fin(double x) { return isfinite(x); }
+};
+template <> struct Math<float> {
+  static __device__ __forceinline__ float ex(float x) { return expf(x); }
+  static __device__ __forceinline__ float lg(float x) { return logf(x); }
+  static __device__ __forceinline__ bool fin(float x) { return isfinite(x); }
+};
+
+// C^o for the rate laws; integer orders by products, others through exp/log.
+template <typename R>
+__device__ __forceinline__ R conc_pow(R C, R o, int has_frac) {
+  R r = (o == R(2)) ? C * C : C;
+  r = (o == R(3)) ? r * C : r;
+  r = (o == R(0)) ? R(1) : r;
+  if (has_frac) {
+    const bool frac = !(o == R(0) || o == R(1) || o == R(2) || o == R(3));
+    if (frac) r = (C > R(0)) ? Math<R>::ex(o * Math<R>::lg(C)) : R(0);
+  }
+  return r;
+}
+
+template <typename R, int G, int RPL, int RRPL, int SPL, int CSRR>
+__global__ void __launch_bounds__(256)
+stev_persistent(const KArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  constexpr int CPW = 64 / G;
+
+  {  // stage the packed mechanism into LDS
+    const uint4 *src = reinterpret_cast<const uint4 *>(a.blob);
+    uint4 *dst = reinterpret_cast<uint4 *>(smem);
+    const int n16 = a.L.bytes >> 4;
+    for (int i = threadIdx.x; i < n16; i += blockDim.x) dst[i] = src[i];
+  }
+  __syncthreads();
+
+  const R *spT = reinterpret_cast<const R *>(smem + a.L.off_sp);
+  const R *rxR = reinterpret_cast<const R *>(smem + a.L.off_rx);
+  const int *rxI = reinterpret_cast<const int *>(smem + a.L.off_rxi);
+  const int *cj = reinterpret_cast<const int *>(smem + a.L.off_cj);
+  const R *cnu = reinterpret_cast<const R *>(smem + a.L.off_cnu);
+
+  const int n_s = a.L.n_s, n_r = a.L.n_r, n_rev = a.L.n_rev, dmax = a.L.dmax;
+  const int has_frac = a.L.has_frac, mixed = a.L.mixed_tmid;
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int gi = lane / G;   // cell slot in the wave
+  const int l = lane % G;    // lane in the group
+
+  // per-wave exchange rows (element index = row * CPW + gi):
+  //   sC  rows 0..n_s-1 concentrations, n_s unit entry, n_s+1 discard
+  //   sQ  rows 0..n_r-1 damped rates,   n_r zero entry,  n_r+1 discard
+  //   sGb rows as sC (Gibbs terms, mixed T_mid only; n_s holds 0)
+  R *ws = reinterpret_cast<R *>(smem + a.lds_mech_bytes + wave * a.wave_bytes);
+  R *sC = ws;
+  R *sQ = sC + (n_s + 2) * CPW;
+  R *sGb = sQ + (n_r + 2) * CPW;
+  if (l == 0) {
+    sC[n_s * CPW + gi] = R(1);
+    sQ[n_r * CPW + gi] = R(0);
+    if (mixed) sGb[n_s * CPW + gi] = R(0);
+  }
+
+  // lane constants: species / reaction rows, LDS element offsets
+  int kk[SPL], crow[SPL];
+  bool kv[SPL];
+#pragma unroll
+  for (int s = 0; s < SPL; ++s) {
+    const int k = l + s * G;
+    kv[s] = k < n_s;
+    kk[s] = kv[s] ? k : n_s;
+    crow[s] = (kv[s] ? k : n_s + 1) * CPW + gi;
+  }
+  int jj[RPL], qrow[RPL], soff[RPL][kMaxPart];
+  bool jrev[RPL];
+#pragma unroll
+  for (int r = 0; r < RPL; ++r) {
+    const int j = l + r * G;
+    const bool jv = j < n_r;
+    jj[r] = jv ? j : n_r;
+    jrev[r] = j < n_rev;
+    qrow[r] = (jv ? j : n_r + 1) * CPW + gi;
+#pragma unroll
+    for (int p = 0; p < kMaxPart; ++p) soff[r][p] = rxI[jj[r] * kMaxPart + p] * CPW + gi;
+  }
+  // species -> reaction CSR offsets held in registers (two 16-bit offsets per
+  // VGPR) when the padded width fits; otherwise read from LDS each iteration
+  const bool csr_reg = (CSRR > 0) && (dmax <= CSRR);
+  unsigned coff[SPL][(CSRR + 1) / 2];
+#pragma unroll
+  for (int s = 0; s < SPL; ++s)
+#pragma unroll
+    for (int e = 0; e < (CSRR + 1) / 2; ++e) {
+      const int e0 = 2 * e, e1 = 2 * e + 1;
+      const unsigned o0 = (e0 < dmax) ? (unsigned)(cj[kk[s] * dmax + e0] * CPW + gi) : (unsigned)(n_r * CPW + gi);
+      const unsigned o1 = (e1 < dmax) ? (unsigned)(cj[kk[s] * dmax + e1] * CPW + gi) : (unsigned)(n_r * CPW + gi);
+      coff[s][e] = csr_reg ? (o0 | (o1 << 16)) : 0u;
+    }
+
+  R *Tg = reinterpret_cast<R *>(a.T);
+  const R *Pg = reinterpret_cast<const R *>(a.P);
+  R *Yg = reinterpret_cast<R *>(a.Y);
+
+  const R ystep = R(a.ystep), alpha = R(a.alpha);
+  const R tol_ring2 = R(a.tol_ring2), tol_freq = R(a.tol_freq);
+  const R r_fac = R(a.r_fac), r_fac_inv = R(a.r_fac_inv), rof_min = R(a.rof_min);
+  const R ln_patm_r = R(a.ln_patm_r);
+  const R rgas = R(kRgas);
+  const double tf = a.tf, dtmax = a.dtmax;
+
+  // per-cell state (replicated over the group where scalar)
+  long long cell = -1;
+  bool active = false, exhausted = false;
+  int st = 0;
+  int it = 0;
+  double t = 0.0;
+  R T = R(1000), P = R(1e5), invP = R(1e-5);
+  R Y[SPL];
+  R rOF[RRPL];
+  R ring[RRPL][kWin];
+#pragma unroll
+  for (int s = 0; s < SPL; ++s) Y[s] = R(0);
+#pragma unroll
+  for (int r = 0; r < RRPL; ++r) {
+    rOF[r] = R(1);
+#pragma unroll
+    for (int m = 0; m < kWin; ++m) ring[r][m] = R(0);
+  }
+
+  // statistics (group leader lanes)
+  long long sum_it = 0;
+  long long max_it = 0;
+  long long n_fail = 0;
+
+  int slot = 0;  // wave-uniform ring slot (rotation leaves |DFT| unchanged)
+  const int K = a.compact_every > 0 ? a.compact_every : 1;
+  int kc = 0;    // iterations until the next refill attempt
+
+  while (true) {
+    // ---- retire finished cells (Sec 2.4) -----------------------------------
+    const bool fin = active && ((st != 0) || !(t < tf) || (it >= a.max_iters));
+    if (__any(fin)) {
+      if (fin) {
+        if (st == 0 && t < tf) st = 2;
+        if (l == 0) Tg[cell] = T;
+#pragma unroll
+        for (int s = 0; s < SPL; ++s)
+          if (kv[s]) Yg[cell * a.ld_cell + (long long)kk[s] * a.ld_sp] = Y[s];
+        if (l == 0) {
+          if (a.iters_out) a.iters_out[cell] = it;
+          if (a.status_out) a.status_out[cell] = (unsigned char)st;
+          sum_it += it;
+          max_it = it > max_it ? it : max_it;
+          n_fail += (st != 0);
+        }
+        active = false;
+      }
+    }
+    // ---- refill free groups from the global cell counter ---------------------
+    if (kc == 0 || !__any(active)) {
+      kc = K;
+      const bool want = !active && !exhausted;
+      const unsigned long long m = __ballot(want && l == 0);
+      if (m) {
+        const int nwant = __popcll(m);
+        unsigned long long base = 0;
+        if (lane == 0) base = atomicAdd(&a.ctl[0], (unsigned long long)nwant);
+        base = __shfl(base, 0);
+        const unsigned long long below = (gi == 0) ? 0ull : (m & ((1ull << (gi * G)) - 1ull));
+        const int rank = __popcll(below);
+        if (want) {
+          const long long c = (long long)base + rank;
+          if (c < a.n_cells) {
+            cell = c;
+            T = Tg[c];
+            P = Pg[c];
+            invP = R(1) / P;
+#pragma unroll
+            for (int s = 0; s < SPL; ++s)
+              Y[s] = kv[s] ? Yg[c * a.ld_cell + (long long)kk[s] * a.ld_sp] : R(0);
+#pragma unroll
+            for (int r = 0; r < RRPL; ++r) rOF[r] = R(1);     // Eq 11
+            t = 0.0;
+            it = 0;
+            st = 0;
+            active = true;
+          } else {
+            exhausted = true;
+          }
+        }
+      }
+      if (!__any(active)) break;
+    }
+    --kc;
+    // a freshly loaded cell with nothing to do (t_f <= 0 or max_iters <= 0)
+    // idles through this pass and retires at the top of the next one
+    const bool run = active && (t < tf) && (it < a.max_iters);
+
+    // ---- one STEV iteration ---------------------------------------------------
+    const R lnT = Math<R>::lg(T);
+    const R invT = R(1) / T;
+
+    // thermo (Eqs 15-16) and mixture sums
+    R cpR[SPL], hRT[SPL], invW[SPL], Wk[SPL];
+    R sumYW = R(0), sumYcp = R(0);
+#pragma unroll
+    for (int s = 0; s < SPL; ++s) {
+      const R *sp = spT + kk[s] * kSpStride;
+      invW[s] = sp[SP_INVW];
+      Wk[s] = sp[SP_W];
+      const R *c = sp + ((T < sp[SP_TMID]) ? SP_LO : SP_HI);
+      const R a1 = c[C_A1], a6 = c[C_A6];
+      cpR[s] = a1 + T * (c[C_CP] + T * (c[C_CP + 1] + T * (c[C_CP + 2] + T * c[C_CP + 3])));
+      hRT[s] = a1 + T * (c[C_H] + T * (c[C_H + 1] + T * (c[C_H + 2] + T * c[C_H + 3]))) + a6 * invT;
+      if (mixed) {
+        sGb[crow[s]] = a1 * (R(1) - lnT) +
+                       T * (c[C_G] + T * (c[C_G + 1] + T * (c[C_G + 2] + T * c[C_G + 3]))) +
+                       a6 * invT - c[C_A7];
+      }
+      const R yw = Y[s] * invW[s];
+      sumYW += yw;
+      sumYcp += yw * cpR[s];
+    }
+    sumYW = grp_sum<G>(sumYW);
+    sumYcp = grp_sum<G>(sumYcp);
+    const R RTs = rgas * T * sumYW;
+    const R rho = P / RTs;             // P Wbar / (R T)
+    const R inv_rho = RTs * invP;
+#pragma unroll
+    for (int s = 0; s < SPL; ++s) {
+      const R yp = Y[s] > R(0) ? Y[s] : R(0);
+      const R yss = yp * yp / (alpha + yp);                          // Eqs 6-7
+      sC[crow[s]] = (yp > R(0)) ? rho * yss * invW[s] : R(0);
+    }
+    wave_lds_sync();
+
+    // rates (Eqs 28-30), damping (Eq 14)
+    R q[RPL];
+    const R lnPRT = ln_patm_r - lnT;
+    const R omlnT = R(1) - lnT;
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) {
+      const R *rr = rxR + jj[r] * kRxStride;
+      R C[kMaxPart];
+#pragma unroll
+      for (int p = 0; p < kMaxPart; ++p) C[p] = sC[soff[r][p]];
+      if (has_frac) {
+#pragma unroll
+        for (int p = 0; p < kMaxPart; ++p) {
+          const R o = rr[RX_ORD + p];
+          if (o != R(1)) C[p] = (C[p] > R(0)) ? Math<R>::ex(o * Math<R>::lg(C[p])) : R(0);
+        }
+      }
+      const R lnkf = rr[RX_LNA] + rr[RX_B] * lnT - rr[RX_TH] * invT;
+      const R kf = Math<R>::ex(lnkf);
+      const R pf = C[0] * C[1] * C[2];
+      R qq = kf * pf;
+      if (n_rev > 0) {
+        R dG;
+        if (!mixed) {
+          const R *d = rr + ((T < rr[RX_TMID]) ? RX_DLO : RX_DHI);
+          dG = d[0] * omlnT + T * (d[1] + T * (d[2] + T * (d[3] + T * d[4]))) + d[5] * invT - d[6];
+        } else {
+          dG = R(0);
+#pragma unroll
+          for (int p = 0; p < kMaxPart; ++p) dG += rr[RX_NU + p] * sGb[soff[r][p]];
+        }
+        const R lnKc = rr[RX_DN] * lnPRT - dG;
+        const R pr = C[3] * C[4] * C[5];
+        const R qrev = kf * (pf - pr * Math<R>::ex(-lnKc));
+        qq = jrev[r] ? qrev : qq;
+      }
+      q[r] = qq;
+      R qe = qq;
+      if (r < RRPL) qe = jrev[r] ? rOF[r < RRPL ? r : 0] * qq : qq;
+      sQ[qrow[r]] = qe;
+    }
+    wave_lds_sync();
+
+    // net production omega = nu^T q_eff, sources, step size (Eqs 1-3)
+    R dYdt[SPL];
+    R sum_hw = R(0);
+    R tst = R(INFINITY);
+#pragma unroll
+    for (int s = 0; s < SPL; ++s) {
+      const R *nu = cnu + kk[s] * dmax;
+      R om = R(0);
+      if (csr_reg) {
+#pragma unroll
+        for (int e = 0; e < (CSRR + 1) / 2; ++e) {
+          if (2 * e < dmax) om += nu[2 * e] * sQ[coff[s][e] & 0xffffu];
+          if (2 * e + 1 < dmax) om += nu[2 * e + 1] * sQ[coff[s][e] >> 16];
+        }
+      } else {
+        const int *jr = cj + kk[s] * dmax;
+        for (int e = 0; e < dmax; ++e) om += nu[e] * sQ[jr[e] * CPW + gi];
+      }
+      const R rk = Wk[s] * om * inv_rho;
+      dYdt[s] = rk;
+      sum_hw += hRT[s] * om;
+      const R rstar = fmax(-rk, R(1e-30));                       // Eq 1
+      const R ystar = (Y[s] < R(1e-20)) ? R(1) : R(0.9) * Y[s];  // Eq 2
+      tst = fmin(tst, fmin(ystep, ystar) / rstar);               // Eq 3
+    }
+    sum_hw = grp_sum<G>(sum_hw);
+    tst = grp_min<G>(tst);
+    const R dTdt = -T * sum_hw * inv_rho / sumYcp;
+    double h = fmin((double)tst, dtmax);   // Eqs 4-5
+    h = fmin(h, tf - t);
+    if (!run) h = 0.0;
+    const R hR = R(h);
+
+    // forward Euler (Eq 18); a non-finite result is not committed
+    const R Tn = T + hR * dTdt;
+    int bad = !(Math<R>::fin(Tn)) || !isfinite(h);
+    R Yn[SPL];
+#pragma unroll
+    for (int s = 0; s < SPL; ++s) {
+      Yn[s] = Y[s] + hR * dYdt[s];
+      bad |= !(Math<R>::fin(Yn[s]));
+    }
+    bad = grp_or<G>(bad);
+    const bool commit = run && !bad;
+    if (run && bad) st = 1;
+    T = commit ? Tn : T;
+#pragma unroll
+    for (int s = 0; s < SPL; ++s) Y[s] = commit ? Yn[s] : Y[s];
+    t = commit ? t + h : t;
+    it += commit ? 1 : 0;
+
+    // ring, DFT and rOF (Eqs 8-13)
+    if (a.dft_on) {
+      R x[RRPL];
+#pragma unroll
+      for (int r = 0; r < RRPL; ++r) x[r] = q[r] * hR;
+      switch (slot) {
+#define STEV_RING_WRITE(M) \
+  case M:                  \
+    _Pragma("unroll") for (int r = 0; r < RRPL; ++r) ring[r][M] = x[r]; \
+    break;
+        STEV_RING_WRITE(0) STEV_RING_WRITE(1) STEV_RING_WRITE(2) STEV_RING_WRITE(3)
+        STEV_RING_WRITE(4) STEV_RING_WRITE(5) STEV_RING_WRITE(6) STEV_RING_WRITE(7)
+        STEV_RING_WRITE(8) STEV_RING_WRITE(9) STEV_RING_WRITE(10) STEV_RING_WRITE(11)
+        STEV_RING_WRITE(12)
+#undef STEV_RING_WRITE
+        default: break;
+      }
+      const bool full = commit && it >= kWin;
+#pragma unroll
+      for (int r = 0; r < RRPL; ++r) {
+        R sp[6], dm[6];
+        R S = ring[r][0];
+#pragma unroll
+        for (int mm = 1; mm <= 6; ++mm) {
+          sp[mm - 1] = ring[r][mm] + ring[r][kWin - mm];
+          dm[mm - 1] = ring[r][mm] - ring[r][kWin - mm];
+          S += sp[mm - 1];
+        }
+        R M2 = R(0);
+#pragma unroll
+        for (int k = 4; k <= 6; ++k) {
+          R re = ring[r][0], im = R(0);
+#pragma unroll
+          for (int mm = 0; mm < 6; ++mm) {
+            re += sp[mm] * R(tw_re(k, mm + 1));
+            im += dm[mm] * R(tw_im(k, mm + 1));
+          }
+          M2 = fmax(M2, re * re + im * im);
+        }
+        const bool ring_eq = (S * S < tol_ring2 * M2) && (fabs(S) < tol_freq);  // Eqs 10, 12
+        const R upd = fmax(fmin(rOF[r] * (ring_eq ? r_fac_inv : r_fac), R(1)), rof_min);  // Eq 13
+        rOF[r] = (full && jrev[r]) ? upd : rOF[r];
+      }
+    }
+    slot = (slot == kWin - 1) ? 0 : slot + 1;
+  }
+
+  // flush statistics: one atomic per wave and counter
+  long long s_it = sum_it, m_it = max_it, n_f = n_fail;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    s_it += __shfl_xor(s_it, off);
+    n_f += __shfl_xor(n_f, off);
+    const long long o = __shfl_xor(m_it, off);
+    m_it = o > m_it ? o : m_it;
+  }
+  if (lane == 0) {
+    if (s_it) atomicAdd(&a.ctl[1], (unsigned long long)s_it);
+    if (m_it) atomicMax(&a.ctl[2], (unsigned long long)m_it);
+    if (n_f) atomicAdd(&a.ctl[3], (unsigned long long)n_f);
+  }
+}
+
+// Fill kernel for the control words (kept out of hipMemsetAsync so that the
+// launch sequence can be captured into a graph).
+__global__ void stev_zero_u64(unsigned long long *p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0ull;
+}
+
+}  // namespace stev
+
+// ---------------------------------------------------------------------------
+// Variant table: (G, RPL, RRPL, SPL) instantiated for double and float.
+// ---------------------------------------------------------------------------
+#include "stev_variants.h"
+
+namespace stev {
+
+#define STEV_INST(R, G, RPL, RRPL, SPL, CSRR) \
+  reinterpret_cast<const void *>(&stev_persistent<R, G, RPL, RRPL, SPL, CSRR>)
+
+const VariantInfo kVariants[] = {
+#define STEV_VARIANT(G, RPL, RRPL, SPL, CSRR)                               \
+  {G, RPL, RRPL, SPL, CSRR, STEV_INST(double, G, RPL, RRPL, SPL, CSRR), \
+   STEV_INST(float, G, RPL, RRPL, SPL, CSRR)},
+    STEV_VARIANT_LIST
+#undef STEV_VARIANT
+};
+const int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
+const void *kZeroKernel = reinterpret_cast<const void *>(&stev_zero_u64);
+
+}  // namespace stev

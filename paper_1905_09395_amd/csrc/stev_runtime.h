@@ -1,0 +1,114 @@
+// Host-side state of libstev (contexts, mechanisms, launch plans).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "../../include/stev.h"
+#include "stev_internal.h"
+
+struct stev_ctx;
+
+// grow-only device buffer charged to the context's HBM budget
+struct Scratch {
+  void *ptr = nullptr;
+  size_t bytes = 0;
+  int ensure(stev_ctx *ctx, size_t want);
+  void release(stev_ctx *ctx);
+};
+
+struct RxnPacked {
+  std::vector<int> sp;                 // participants in input order
+  std::vector<double> nu, ord;
+  int slot_sp[stev::kMaxPart];         // kernel slots: 0..2 reactants, 3..5 products
+  double slot_nu[stev::kMaxPart], slot_ord[stev::kMaxPart];
+  double lnA_SI = 0, b = 0, theta = 0, dN = 0, tmid = 1000.0;
+  double dlo[7], dhi[7];               // Gibbs polynomial coefficient sums
+  bool rev = false;
+  bool zero_order_rev = false;         // a participant without rate-law slot
+};
+
+// thermo network attached to a mechanism
+struct MlpHost {
+  int enabled = 0;
+  int hidden = 0;
+  double T_lo = 300, T_hi = 3000;
+  std::vector<float> master;        // FP32 weights (export layout) + z-score constants
+  void *dev = nullptr;              // one device buffer holding every array below
+  size_t dev_bytes = 0;
+  stev::MlpDev devv{};
+  stev::MlpDev &dev_view() { return devv; }
+};
+
+struct stev_mech {
+  int n_s = 0, n_r = 0, n_rev = 0, max_part = 0, has_frac = 0, mixed_tmid = 0, dmax = 1;
+  std::vector<double> W, nasa_lo, nasa_hi, T_mid;
+  std::vector<RxnPacked> rx;        // packed order: reversible first
+  std::vector<int> orig_of_new;
+  std::vector<int> csr_ptr, csr_j;
+  std::vector<double> csr_nu;
+  void *blob[2] = {nullptr, nullptr};
+  size_t blob_bytes[2] = {0, 0};
+  stev::MechLayout L[2];
+  struct {
+    int enabled = 0;
+    stev::MlpDev dev{};
+  } mlp;
+  MlpHost mlph;
+};
+
+struct LaunchPlan {
+  int variant = -1, G = 1, waves = 8, block = 512, grid = 1, lds = 0, wave_bytes = 0;
+  int occ = 1, compact = 1;
+  const void *fn = nullptr;
+};
+
+struct ServeState;   // stev_serve.hip
+
+struct stev_ctx {
+  int device = 0;
+  int n_cu = 0;
+  int max_lds = 65536;
+  int max_lds_cu = 65536;
+  char arch[64] = {0};
+  hipStream_t own_stream = nullptr;
+  hipStream_t stream = nullptr;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  size_t budget = 0, used = 0;
+  std::mutex mem_mu, err_mu, call_mu;
+  std::string err;
+  unsigned long long *ctl = nullptr;       // device control words
+  unsigned long long *ctl_host = nullptr;  // pinned mirror
+  Scratch sT, sP, sY, sI, sS;
+  ServeState *serve = nullptr;
+  std::map<std::string, stev_params> tune_cache;
+};
+
+int stev_fail(stev_ctx *ctx, int code, const char *fmt, ...);
+int dev_alloc(stev_ctx *ctx, void **p, size_t bytes);
+void dev_free(stev_ctx *ctx, void *p, size_t bytes);
+bool is_device_ptr(const void *p);
+int pick_variant(const stev_mech *m, int precision, int want_G);
+int validate_params(stev_ctx *ctx, const stev_mech *m, const stev_params &p, double dt_flow);
+int plan_launch(stev_ctx *ctx, const stev_mech *m, const stev_params &p, long long n_cells,
+                LaunchPlan &lp);
+int fill_kargs(stev_ctx *ctx, const stev_mech *m, const stev_params &p, double dt_flow,
+               stev::KArgs &a);
+int launch_zero(stev_ctx *ctx, unsigned long long *p, int n, hipStream_t s);
+int launch_stev(stev_ctx *ctx, const LaunchPlan &lp, stev::KArgs &a, hipStream_t s);
+
+// thermo network (stev_mlp.hip)
+void mlp_release(stev_ctx *ctx, stev_mech *m);
+const void *mlp_kernel_for(int variant, int precision);
+int mlp_wave_bytes(const stev_mech *m, const stev_params &p, int G);
+
+// serving (stev_serve.hip)
+void serve_stop(stev_ctx *ctx);

@@ -1,0 +1,324 @@
+"""ctypes binding of libstev.so (argument marshalling only).
+
+Every step of the integration runs in the library's HIP kernels; this module
+never computes any part of the method.  If the compiled library is missing,
+loading fails loudly -- there is no CPU fallback.
+
+Arrays may be torch tensors (device or host) or numpy arrays (host); torch is
+used only for device memory and streams.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+import re
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libstev.so")
+HEADER = os.path.join(os.path.dirname(_HERE), "include", "stev.h")
+
+STEV_OK, STEV_EINVAL, STEV_ENOMEM, STEV_EAGAIN, STEV_ENOTFOUND, STEV_EDEVICE, STEV_ECELLS = range(7)
+F64, F32 = 0, 1
+THERMO_POLY, THERMO_MLP = 0, 1
+ERR_NAMES = {0: "STEV_OK", 1: "STEV_EINVAL", 2: "STEV_ENOMEM", 3: "STEV_EAGAIN",
+             4: "STEV_ENOTFOUND", 5: "STEV_EDEVICE", 6: "STEV_ECELLS"}
+
+
+class StevError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{ERR_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class MechDesc(C.Structure):
+    _fields_ = [("n_species", C.c_int32), ("n_reactions", C.c_int32),
+                ("W", C.c_void_p), ("nasa_lo", C.c_void_p), ("nasa_hi", C.c_void_p),
+                ("T_mid", C.c_void_p), ("rxn_ptr", C.c_void_p), ("sp_idx", C.c_void_p),
+                ("nu", C.c_void_p), ("order", C.c_void_p), ("A", C.c_void_p),
+                ("b", C.c_void_p), ("Ea", C.c_void_p), ("reversible", C.c_void_p)]
+
+
+class Params(C.Structure):
+    _fields_ = [("precision", C.c_int32), ("thermo", C.c_int32),
+                ("ystep_max", C.c_double), ("delta_max", C.c_double), ("alpha", C.c_double),
+                ("tol_ring", C.c_double), ("tol_freq", C.c_double), ("r_fac", C.c_double),
+                ("rof_min", C.c_double), ("dft_window", C.c_int32),
+                ("lanes_per_cell", C.c_int32), ("max_iters", C.c_int64),
+                ("waves_per_wg", C.c_int32), ("compact_every", C.c_int32),
+                ("grid_wgs", C.c_int32), ("reserved", C.c_int32)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("n_cells", C.c_int64), ("total_iters", C.c_int64),
+                ("max_cell_iters", C.c_int64), ("n_failed", C.c_int64),
+                ("kernel_ms", C.c_double), ("total_ms", C.c_double),
+                ("lanes_per_cell", C.c_int32), ("waves_per_wg", C.c_int32),
+                ("grid_wgs", C.c_int32), ("compact_every", C.c_int32),
+                ("latency_ms", C.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class MlpCfg(C.Structure):
+    _fields_ = [("hidden", C.c_int32), ("epochs", C.c_int32), ("n_samples", C.c_int64),
+                ("batch", C.c_int32), ("seed", C.c_int32), ("lr", C.c_double),
+                ("T_lo", C.c_double), ("T_hi", C.c_double), ("holdout_frac", C.c_double)]
+
+
+class MlpReport(C.Structure):
+    _fields_ = [("train_loss", C.c_double), ("test_loss", C.c_double),
+                ("max_rel_err_cp", C.c_double), ("mean_rel_err_cp", C.c_double),
+                ("max_rel_err_h", C.c_double), ("mean_rel_err_h", C.c_double),
+                ("train_ms", C.c_double), ("steps", C.c_int64)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+_lib = None
+
+
+def header_symbols():
+    """Entry points declared in include/stev.h."""
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"\b(stev_[a-z_0-9]+)\s*\(", text)))
+
+
+def load():
+    """Load libstev.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"libstev.so not built ({LIB_PATH}); run __graft_entry__.build()")
+    L = C.CDLL(LIB_PATH)
+    vp, i32, i64, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+    L.stev_default_params.argtypes = [C.POINTER(Params)]
+    L.stev_default_params.restype = None
+    L.stev_init.argtypes = [C.POINTER(vp), C.c_int, C.c_size_t]
+    L.stev_set_stream.argtypes = [vp, vp]
+    L.stev_create_mechanism.argtypes = [vp, C.POINTER(MechDesc), C.POINTER(vp)]
+    L.stev_integrate.argtypes = [vp, vp, i64, vp, vp, vp, i64, i64, dbl, C.POINTER(Params),
+                                 vp, vp, C.POINTER(Stats)]
+    L.stev_integrate_batched.argtypes = [vp, i32, C.POINTER(vp), C.POINTER(i64), C.POINTER(vp),
+                                         C.POINTER(vp), C.POINTER(vp), C.POINTER(i64),
+                                         C.POINTER(i64), dbl, C.POINTER(Params), C.POINTER(vp),
+                                         C.POINTER(vp), C.POINTER(Stats)]
+    L.stev_submit.argtypes = [vp, vp, i64, vp, vp, vp, i64, i64, dbl, C.POINTER(Params), vp, vp,
+                              C.POINTER(C.c_uint64)]
+    L.stev_poll.argtypes = [vp, C.c_uint64, C.POINTER(Stats)]
+    L.stev_train_thermo_mlp.argtypes = [vp, vp, C.POINTER(MlpCfg), C.POINTER(MlpReport)]
+    L.stev_get_thermo_mlp.argtypes = [vp, vp, vp, C.POINTER(i64)]
+    L.stev_set_thermo_mlp.argtypes = [vp, vp, i32, dbl, dbl, vp, i64]
+    L.stev_autotune.argtypes = [vp, vp, i64, vp, vp, vp, i64, i64, dbl, C.POINTER(Params)]
+    L.stev_model_flops.argtypes = [vp, i32, C.POINTER(dbl)]
+    L.stev_model_flops.restype = dbl
+    L.stev_destroy_mechanism.argtypes = [vp, vp]
+    L.stev_destroy_mechanism.restype = None
+    L.stev_shutdown.argtypes = [vp]
+    L.stev_shutdown.restype = None
+    L.stev_last_error.argtypes = [vp]
+    L.stev_last_error.restype = C.c_char_p
+    _lib = L
+    return L
+
+
+def default_params(**kw):
+    p = Params()
+    load().stev_default_params(C.byref(p))
+    for k, v in kw.items():
+        if not hasattr(p, k):
+            raise KeyError(k)
+        setattr(p, k, v)
+    return p
+
+
+def _ptr(x):
+    """(address, keepalive) for a torch tensor / numpy array / None."""
+    if x is None:
+        return None, None
+    if hasattr(x, "data_ptr"):
+        return x.data_ptr(), x
+    if isinstance(x, np.ndarray):
+        if not x.flags["C_CONTIGUOUS"]:
+            raise ValueError("numpy arrays must be C-contiguous")
+        return x.ctypes.data, x
+    raise TypeError(f"unsupported array type {type(x)}")
+
+
+class Mechanism:
+    def __init__(self, ctx, mech):
+        self.ctx = ctx
+        self.mech = mech
+        self.n_s = int(mech["n_s"])
+        self.n_r = int(mech["n_r"])
+        keep = {
+            "W": np.ascontiguousarray(mech["W"], dtype=np.float64),
+            "nasa_lo": np.ascontiguousarray(mech["nasa_lo"], dtype=np.float64),
+            "nasa_hi": np.ascontiguousarray(mech["nasa_hi"], dtype=np.float64),
+            "T_mid": np.ascontiguousarray(mech["T_mid"], dtype=np.float64),
+            "rxn_ptr": np.ascontiguousarray(mech["rxn_ptr"], dtype=np.int32),
+            "sp_idx": np.ascontiguousarray(mech["sp_idx"], dtype=np.int32),
+            "nu": np.ascontiguousarray(mech["nu"], dtype=np.float64),
+            "order": np.ascontiguousarray(mech["order"], dtype=np.float64),
+            "A": np.ascontiguousarray(mech["A"], dtype=np.float64),
+            "b": np.ascontiguousarray(mech["b"], dtype=np.float64),
+            "Ea": np.ascontiguousarray(mech["Ea"], dtype=np.float64),
+            "reversible": np.ascontiguousarray(mech["reversible"], dtype=np.uint8),
+        }
+        d = MechDesc(self.n_s, self.n_r, *[keep[f].ctypes.data for f in (
+            "W", "nasa_lo", "nasa_hi", "T_mid", "rxn_ptr", "sp_idx", "nu", "order", "A", "b",
+            "Ea", "reversible")])
+        h = C.c_void_p()
+        ctx._check(ctx.lib.stev_create_mechanism(ctx.h, C.byref(d), C.byref(h)))
+        self.h = h
+
+    def model_flops(self, thermo=THERMO_POLY):
+        tr = C.c_double()
+        f = self.ctx.lib.stev_model_flops(self.h, thermo, C.byref(tr))
+        return f, tr.value
+
+    def close(self):
+        if self.h:
+            self.ctx.lib.stev_destroy_mechanism(self.ctx.h, self.h)
+            self.h = None
+
+
+class Context:
+    """One libstev context on one HIP device."""
+
+    def __init__(self, device=0, hbm_budget=0):
+        self.lib = load()
+        h = C.c_void_p()
+        rc = self.lib.stev_init(C.byref(h), int(device), int(hbm_budget))
+        if rc != STEV_OK:
+            raise StevError(rc, "stev_init failed")
+        self.h = h
+
+    def last_error(self):
+        s = self.lib.stev_last_error(self.h)
+        return s.decode() if s else ""
+
+    def _check(self, rc, ok=(STEV_OK,)):
+        if rc not in ok:
+            raise StevError(rc, self.last_error())
+        return rc
+
+    def set_stream(self, stream):
+        """Launch on a torch.cuda.Stream (or raw hipStream_t int); None = own stream."""
+        if stream is None:
+            addr = None
+        elif hasattr(stream, "cuda_stream"):
+            addr = stream.cuda_stream
+        else:
+            addr = int(stream)
+        self._check(self.lib.stev_set_stream(self.h, addr))
+
+    def mechanism(self, mech):
+        return Mechanism(self, mech)
+
+    def integrate(self, mech, T, P, Y, dt_flow, params=None, iters=None, status=None,
+                  ld_cell=None, ld_species=None, allow_failed=False):
+        """Integrate in place.  Y is [n_cells, n_s] unless strides are given.
+
+        Returns (rc, stats dict).  rc is STEV_OK or STEV_ECELLS (failed cells,
+        only when allow_failed).
+        """
+        params = params or default_params()
+        n = int(T.shape[0])
+        if ld_cell is None:
+            ld_cell = int(Y.shape[1]) if len(Y.shape) == 2 else mech.n_s
+        if ld_species is None:
+            ld_species = 1
+        pT, kT = _ptr(T)
+        pP, kP = _ptr(P)
+        pY, kY = _ptr(Y)
+        pI, kI = _ptr(iters)
+        pS, kS = _ptr(status)
+        st = Stats()
+        rc = self.lib.stev_integrate(self.h, mech.h, n, pT, pP, pY, int(ld_cell), int(ld_species),
+                                     float(dt_flow), C.byref(params), pI, pS, C.byref(st))
+        self._check(rc, (STEV_OK, STEV_ECELLS) if allow_failed else (STEV_OK,))
+        return rc, st.as_dict()
+
+    def integrate_batched(self, mechs, Ts, Ps, Ys, dt_flow, params=None, iters=None,
+                          status=None, allow_failed=False):
+        params = params or default_params()
+        nb = len(Ts)
+        keep = []
+        arr = lambda t, xs: (t * nb)(*xs)
+        ph = arr(C.c_void_p, [m.h for m in mechs])
+        pn = arr(C.c_int64, [int(t.shape[0]) for t in Ts])
+        pT = arr(C.c_void_p, [_ptr(t)[0] for t in Ts])
+        pP = arr(C.c_void_p, [_ptr(t)[0] for t in Ps])
+        pY = arr(C.c_void_p, [_ptr(t)[0] for t in Ys])
+        lc = arr(C.c_int64, [int(y.shape[1]) for y in Ys])
+        ls = arr(C.c_int64, [1] * nb)
+        pI = arr(C.c_void_p, [_ptr(x)[0] for x in iters]) if iters else None
+        pS = arr(C.c_void_p, [_ptr(x)[0] for x in status]) if status else None
+        keep.extend([Ts, Ps, Ys, iters, status])
+        st = Stats()
+        rc = self.lib.stev_integrate_batched(self.h, nb, ph, pn, pT, pP, pY, lc, ls,
+                                             float(dt_flow), C.byref(params), pI, pS,
+                                             C.byref(st))
+        self._check(rc, (STEV_OK, STEV_ECELLS) if allow_failed else (STEV_OK,))
+        return rc, st.as_dict()
+
+    def submit(self, mech, T, P, Y, dt_flow, params=None, iters=None, status=None):
+        params = params or default_params()
+        n = int(T.shape[0])
+        tk = C.c_uint64()
+        rc = self.lib.stev_submit(self.h, mech.h, n, _ptr(T)[0], _ptr(P)[0], _ptr(Y)[0],
+                                  int(Y.shape[1]), 1, float(dt_flow), C.byref(params),
+                                  _ptr(iters)[0], _ptr(status)[0], C.byref(tk))
+        self._check(rc)
+        return tk.value
+
+    def poll(self, ticket):
+        st = Stats()
+        rc = self.lib.stev_poll(self.h, C.c_uint64(ticket), C.byref(st))
+        if rc not in (STEV_OK, STEV_EAGAIN, STEV_ECELLS):
+            raise StevError(rc, self.last_error())
+        return rc, st.as_dict()
+
+    def train_thermo_mlp(self, mech, **cfg):
+        c = MlpCfg(32, 4, 1 << 20, 4096, 104, 3e-3, 300.0, 3000.0, 0.125)
+        for k, v in cfg.items():
+            setattr(c, k, v)
+        rep = MlpReport()
+        self._check(self.lib.stev_train_thermo_mlp(self.h, mech.h, C.byref(c), C.byref(rep)))
+        return rep.as_dict()
+
+    def get_thermo_mlp(self, mech):
+        n = C.c_int64(0)
+        self._check(self.lib.stev_get_thermo_mlp(self.h, mech.h, None, C.byref(n)))
+        buf = np.zeros(n.value, dtype=np.float32)
+        self._check(self.lib.stev_get_thermo_mlp(self.h, mech.h, buf.ctypes.data, C.byref(n)))
+        return buf
+
+    def set_thermo_mlp(self, mech, hidden, T_lo, T_hi, values):
+        v = np.ascontiguousarray(values, dtype=np.float32)
+        self._check(self.lib.stev_set_thermo_mlp(self.h, mech.h, int(hidden), float(T_lo),
+                                                 float(T_hi), v.ctypes.data, len(v)))
+
+    def autotune(self, mech, T, P, Y, dt_flow, params=None):
+        params = params or default_params()
+        self._check(self.lib.stev_autotune(self.h, mech.h, int(T.shape[0]), _ptr(T)[0],
+                                           _ptr(P)[0], _ptr(Y)[0], int(Y.shape[1]), 1,
+                                           float(dt_flow), C.byref(params)))
+        return params
+
+    def close(self):
+        if self.h:
+            self.lib.stev_shutdown(self.h)
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()

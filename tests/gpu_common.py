@@ -1,0 +1,129 @@
+"""Helpers shared by the GPU tests: run the library through the C ABI and
+judge it against the FP64 oracle.  Expected values always come from the
+oracle (never from the GPU path).
+
+Conditioning.  The STEV iteration (explicit Euler whose step is a min over
+species of a non-smooth limiter) is chaotic for a minority of cells: in the
+oracle itself, a relative perturbation of 1e-15 of the initial state changes
+nearly depleted species by O(1) at t_f.  No implementation whose arithmetic
+differs at the last bit (exp/log, FMA contraction, summation order) can match
+such cells to 1e-9.  The oracle therefore also reports, per cell, the spread
+of its own results over an ensemble of eight perturbed runs (initial state
+moved by a few ulps of the precision under test; for FP32 also rounding
+noise injected into the net rates):
+
+* well-conditioned cells (ensemble spread < tolerance/100 on T and on every
+  judged Y, equal iteration counts) must meet the stated tolerance, and in
+  FP64 the same iteration count;
+* ill-conditioned cells must lie within C = 10 times the oracle's own
+  ensemble spread (or within the tolerance, whichever is larger).
+The fraction of ill-conditioned cells is reported with every result.
+"""
+
+import sys
+
+import numpy as np
+
+import oracle
+from paper_1905_09395_amd import stev
+
+# tolerances stated by the design: FP64 path 1e-9 relative on T and on every
+# Y_k > 1e-10; FP32 (and MLP) paths 1e-4 on T and 1e-3 on Y_k > 1e-6
+TOL = {stev.F64: (1e-9, 1e-9, 1e-10), stev.F32: (1e-4, 1e-3, 1e-6)}
+# ensemble members: initial-state perturbation of a few ulps of the precision
+# under test plus, for FP32, the oracle's rounding-noise instrument on every
+# net rate at the accuracy FP32 keeps the equilibrium constant to: ln K is a
+# sum of terms of magnitude ~60 evaluated in FP32, so K (and with it the
+# reverse rate against the forward one) carries ~60 * 2^-24 = 4e-6 relative
+# error
+ENS_EPS = {stev.F64: 2e-15, stev.F32: 2.4e-7}
+ENS_NOISE = {stev.F64: 0.0, stev.F32: 4e-6}
+SPREAD_FACTOR = 10.0
+ENS_MEMBERS = ((1, 0), (-1, 0), (0, 1), (0, -1), (1, 1), (-1, -1), (1, -1), (-1, 1))
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def run_gpu(ctx, m, T, P, Y, dt, precision=stev.F64, **kw):
+    import torch
+    dtype = torch.float64 if precision == stev.F64 else torch.float32
+    Tt = torch.tensor(np.asarray(T), dtype=dtype, device="cuda")
+    Pt = torch.tensor(np.asarray(P), dtype=dtype, device="cuda")
+    Yt = torch.tensor(np.asarray(Y), dtype=dtype, device="cuda").contiguous()
+    n = Tt.shape[0]
+    it = torch.zeros(n, dtype=torch.int32, device="cuda")
+    stt = torch.zeros(n, dtype=torch.uint8, device="cuda")
+    allow = kw.pop("allow_failed", False)
+    prm = stev.default_params(precision=precision, **kw)
+    rc, stats = ctx.integrate(m, Tt, Pt, Yt, dt, params=prm, iters=it, status=stt,
+                              allow_failed=allow)
+    torch.cuda.synchronize()
+    return dict(T=Tt.cpu().double().numpy(), Y=Yt.cpu().double().numpy(),
+                iters=it.cpu().numpy().astype(np.int64), status=stt.cpu().numpy(),
+                rc=rc, stats=stats)
+
+
+def oracle_ensemble(om, T, P, Y, dt, precision=stev.F64, **kw):
+    """Oracle result plus the spread of its own results over perturbed inputs."""
+    base = oracle.integrate(om, T, P, Y, dt, **kw)
+    eps = ENS_EPS[precision]
+    noise = ENS_NOISE[precision]
+    dT = np.zeros_like(base["T"])
+    dY = np.zeros_like(base["Y"])
+    dI = np.zeros_like(base["iters"])
+    for i, (sT, sY) in enumerate(ENS_MEMBERS):
+        r = oracle.integrate(om, np.asarray(T) * (1 + sT * eps), P,
+                             np.asarray(Y) * (1 + sY * eps), dt, noise_eps=noise,
+                             noise_seed=1000 + i, **kw)
+        ok = np.isfinite(r["T"]) & np.isfinite(base["T"])
+        dT = np.maximum(dT, np.where(ok, np.abs(r["T"] - base["T"]), 0.0))
+        dY = np.maximum(dY, np.where(ok[:, None], np.abs(r["Y"] - base["Y"]), 0.0))
+        dI = np.maximum(dI, np.abs(r["iters"] - base["iters"]))
+    base["spread_T"] = dT
+    base["spread_Y"] = dY
+    base["spread_iters"] = dI
+    return base
+
+
+def judge(g, o, precision, label="", iters_equal=None):
+    """Check GPU result g against oracle ensemble o; returns a summary dict."""
+    tT, tY, thr = TOL[precision]
+    if iters_equal is None:
+        iters_equal = precision == stev.F64
+    fin = np.isfinite(o["T"])
+    Tref = np.where(fin, o["T"], 1.0)
+    mask = (o["Y"] > thr) & fin[:, None]
+    eT = np.where(fin, np.abs(g["T"] - o["T"]), 0.0)
+    eY = np.where(mask, np.abs(g["Y"] - o["Y"]), 0.0)
+    relT = eT / np.abs(Tref)
+    relY = np.where(mask, eY / np.where(mask, o["Y"], 1.0), 0.0).max(axis=1)
+    sprT = o["spread_T"] / np.abs(Tref)
+    sprY = np.where(mask, o["spread_Y"] / np.where(mask, o["Y"], 1.0), 0.0).max(axis=1)
+    well = (sprT < tT / 100) & (sprY < tY / 100) & (o["spread_iters"] == 0)
+    ok_well = (relT <= tT) & (relY <= tY)
+    if iters_equal:
+        ok_well &= g["iters"] == o["iters"]
+    allowT = np.maximum(tT * np.abs(Tref), SPREAD_FACTOR * o["spread_T"])
+    allowY = np.maximum(tY * np.abs(o["Y"]), SPREAD_FACTOR * o["spread_Y"])
+    ok_ill = (eT <= allowT) & np.all(np.where(mask, eY <= allowY, True), axis=1)
+    ok = np.where(well, ok_well, ok_ill)
+    s = dict(n=len(ok), n_ill=int(np.sum(~well)), n_fail=int(np.sum(~ok)),
+             max_rel_T_well=float(relT[well].max(initial=0.0)),
+             max_rel_Y_well=float(relY[well].max(initial=0.0)),
+             max_rel_T_all=float(relT.max(initial=0.0)),
+             max_rel_Y_all=float(relY.max(initial=0.0)),
+             iter_mismatch_well=int(np.sum(well & (g["iters"] != o["iters"]))))
+    say(f"[{label}] n={s['n']} ill-conditioned={s['n_ill']} fail={s['n_fail']} "
+        f"well: max_rel_T={s['max_rel_T_well']:.2e} max_rel_Y={s['max_rel_Y_well']:.2e} "
+        f"iter_mismatch={s['iter_mismatch_well']} | all: max_rel_T={s['max_rel_T_all']:.2e} "
+        f"max_rel_Y={s['max_rel_Y_all']:.2e}")
+    bad = np.where(~ok)[0]
+    for c in bad[:5]:
+        say(f"    cell {c} well={well[c]} relT={relT[c]:.2e} relY={relY[c]:.2e} "
+            f"it g/o={g['iters'][c]}/{o['iters'][c]} sprT={sprT[c]:.1e} sprY={sprY[c]:.1e}")
+    assert np.array_equal(g["status"], o["status"]), label
+    assert s["n_fail"] == 0, label
+    return s

@@ -190,6 +190,24 @@ int stev_get_thermo_mlp(stev_ctx *ctx, const stev_mech *mech, float *values, int
 int stev_set_thermo_mlp(stev_ctx *ctx, stev_mech *mech, int32_t hidden, double T_lo,
                         double T_hi, const float *values, int64_t n_values);
 
+/* Loss and gradient of a thermo network on the GPU, with the same kernels
+ * the trainer uses (exposed so the gradients can be checked).  params:
+ * FP32 [hidden + hidden + hidden^2 + hidden + n_out*hidden + n_out] in the
+ * layout above; x [n] normalised inputs; target [n][n_out]; grad receives
+ * d(mean squared error)/d(params); all host pointers.  hidden must be 32,
+ * n_out <= 128. */
+int stev_mlp_loss_grad(stev_ctx *ctx, int32_t hidden, int32_t n_out, const float *params,
+                       int64_t n, const float *x, const float *target, float *grad,
+                       double *loss);
+
+/* Evaluate cp/R and h/R ([n][n_species], row-major) at n temperatures on
+ * the GPU, with the NASA-7 polynomials (STEV_THERMO_POLY, FP64) or with the
+ * attached network exactly as the integrator evaluates it
+ * (STEV_THERMO_MLP: BF16 MFMA, FP32 accumulation, polynomial fallback
+ * outside the trained range).  Host pointers. */
+int stev_thermo_eval(stev_ctx *ctx, const stev_mech *mech, int32_t thermo, int64_t n,
+                     const double *T, double *cp_R, double *h_R);
+
 /* Pick lanes_per_cell, waves_per_wg and compact_every by timing trial runs
  * on a private copy of up to n_cells_hint synthetic cells drawn from the
  * given device state (read-only).  Results are written to *inout and cached

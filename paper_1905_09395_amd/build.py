@@ -13,6 +13,10 @@ ARCH = "gfx950"
 
 HIP_FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
+    # contract a*b+c only inside one source expression, never across
+    # statements: every kernel variant then rounds the same arithmetic the
+    # same way, whatever code the compiler places around it
+    "-ffp-contract=on",
     # packed FP32 forms stay off (see the design notes on numerics)
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function", "-Wno-unused-variable",

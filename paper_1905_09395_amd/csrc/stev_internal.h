@@ -59,23 +59,30 @@ struct MechLayout {
   int off_cnu;         // R   [n_s+1][dmax]     nu (0 on padding)
 };
 
-// Thermo network attached to a mechanism (Sec 3): 1 -> H -> H -> 2 n_s.
+// Thermo network attached to a mechanism (Sec 3): 1 -> 32 -> 32 -> 2 n_s.
+// Its device blob (FP32 vectors, then bf16 hi/lo MFMA operand tiles) is
+// staged to LDS after the mechanism blob.
+struct MlpBlobLayout {
+  int nop;          // outputs padded to a multiple of 16
+  int n_out;        // 2 n_s: cp/R of every species, then h/R
+  int off_w1, off_b1, off_b2, off_b3, off_mean, off_std, off_w2, off_w3;
+  int bytes;
+};
+
 struct MlpDev {
-  int enabled, hidden;
-  float T_lo, T_hi, x_scale, x_shift;   // x = (T - x_shift) * x_scale
-  const float *w1, *b1;                 // [H]
-  const float *b2;                      // [H]
-  const uint16_t *w2hi, *w2lo;          // bf16 [H][H]  (row = output unit)
-  const float *b3;                      // [2 n_s]
-  const uint16_t *w3hi, *w3lo;          // bf16 [2 n_s padded to 64][H]
-  const float *out_mean, *out_std;      // [2 n_s]: cp/R then h/R
+  int enabled;
+  float T_lo, T_hi;         // trained range; outside it the polynomials are used
+  float x_shift, x_scale;   // x = (T - x_shift) * x_scale
+  const void *blob;
+  MlpBlobLayout L;
 };
 
 struct KArgs {
   const void *blob;
   MechLayout L;
   int wave_bytes;          // per-wave LDS scratch
-  int lds_mech_bytes;      // blob bytes staged (aligned)
+  int exch_bytes;          // of which the exchange rows (the rest: network scratch)
+  int lds_mech_bytes;      // blob bytes staged (mechanism + network, aligned)
   // cells
   long long n_cells;
   void *T;

@@ -21,6 +21,7 @@
 // wave claims all new cells with one atomic and hands them out by ballot
 // rank.  A wave exits when the counter is exhausted and its groups are idle.
 #include "stev_internal.h"
+#include "stev_thermo.h"
 
 namespace stev {
 
@@ -145,17 +146,23 @@ __device__ __forceinline__ R conc_pow(R C, R o, int has_frac) {
   return r;
 }
 
-template <typename R, int G, int RPL, int RRPL, int SPL, int CSRR>
+template <typename R, int G, int RPL, int RRPL, int SPL, int CSRR, bool MLP>
 __global__ void __launch_bounds__(256)
 stev_persistent(const KArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   constexpr int CPW = 64 / G;
+  constexpr int NT = (CPW + 15) / 16;   // 16-cell MFMA column tiles per wave
 
-  {  // stage the packed mechanism into LDS
+  {  // stage the packed mechanism (and the thermo network) into LDS
     const uint4 *src = reinterpret_cast<const uint4 *>(a.blob);
     uint4 *dst = reinterpret_cast<uint4 *>(smem);
     const int n16 = a.L.bytes >> 4;
     for (int i = threadIdx.x; i < n16; i += blockDim.x) dst[i] = src[i];
+    if constexpr (MLP) {
+      const uint4 *ws = reinterpret_cast<const uint4 *>(a.mlp.blob);
+      uint4 *wd = reinterpret_cast<uint4 *>(smem + a.L.bytes);
+      for (int i = threadIdx.x; i < (a.mlp.L.bytes >> 4); i += blockDim.x) wd[i] = ws[i];
+    }
   }
   __syncthreads();
 
@@ -184,6 +191,14 @@ stev_persistent(const KArgs a) {
     sC[n_s * CPW + gi] = R(1);
     sQ[n_r * CPW + gi] = R(0);
     if (mixed) sGb[n_s * CPW + gi] = R(0);
+  }
+  // thermo-network scratch: layer activations (bf16 hi/lo planes) and outputs
+  const unsigned char *wnet = smem + a.L.bytes;
+  __bf16 *act1 = reinterpret_cast<__bf16 *>(reinterpret_cast<unsigned char *>(ws) + a.exch_bytes);
+  __bf16 *act2 = act1 + 2 * NT * 16 * kMlpH;
+  float *mout = reinterpret_cast<float *>(act2 + 2 * NT * 16 * kMlpH);
+  if constexpr (MLP) {   // columns without a cell stay zero
+    for (int i = lane; i < 4 * NT * 16 * kMlpH; i += 64) act1[i] = (__bf16)0.0f;
   }
 
   // lane constants: species / reaction rows, LDS element offsets
@@ -257,7 +272,7 @@ stev_persistent(const KArgs a) {
   long long max_it = 0;
   long long n_fail = 0;
 
-  int slot = 0;  // wave-uniform ring slot (rotation leaves |DFT| unchanged)
+  int rs = 0;    // this cell's ring slot: sample i goes to slot i mod 13
   const int K = a.compact_every > 0 ? a.compact_every : 1;
   int kc = 0;    // iterations until the next refill attempt
 
@@ -307,6 +322,7 @@ stev_persistent(const KArgs a) {
             for (int r = 0; r < RRPL; ++r) rOF[r] = R(1);     // Eq 11
             t = 0.0;
             it = 0;
+            rs = 0;
             st = 0;
             active = true;
           } else {
@@ -325,9 +341,23 @@ stev_persistent(const KArgs a) {
     const R lnT = Math<R>::lg(T);
     const R invT = R(1) / T;
 
-    // thermo (Eqs 15-16) and mixture sums
+    // thermo (Eqs 15-16) and mixture sums; with the network, cp and h come from
+    // its outputs for cells inside the trained range (Sec 3)
     R cpR[SPL], hRT[SPL], invW[SPL], Wk[SPL];
     R sumYW = R(0), sumYcp = R(0);
+    bool use_net = false;
+    if constexpr (MLP) {
+      const float x = (float)(T - R(a.mlp.x_shift)) * a.mlp.x_scale;
+#pragma unroll
+      for (int j = 0; j < (kMlpH + G - 1) / G; ++j) {
+        const int u = l + j * G;
+        if (u < kMlpH) mlp_layer1(wnet, a.mlp.L, act1, NT * 16, gi, u, x);
+      }
+      wave_lds_sync();
+      mlp_layers23<NT>(wnet, a.mlp.L, act1, act2, mout);
+      use_net = (T >= R(a.mlp.T_lo)) && (T <= R(a.mlp.T_hi));
+    }
+    const bool need_poly = !MLP || __any(!use_net);
 #pragma unroll
     for (int s = 0; s < SPL; ++s) {
       const R *sp = spT + kk[s] * kSpStride;
@@ -335,8 +365,17 @@ stev_persistent(const KArgs a) {
       Wk[s] = sp[SP_W];
       const R *c = sp + ((T < sp[SP_TMID]) ? SP_LO : SP_HI);
       const R a1 = c[C_A1], a6 = c[C_A6];
-      cpR[s] = a1 + T * (c[C_CP] + T * (c[C_CP + 1] + T * (c[C_CP + 2] + T * c[C_CP + 3])));
-      hRT[s] = a1 + T * (c[C_H] + T * (c[C_H + 1] + T * (c[C_H + 2] + T * c[C_H + 3]))) + a6 * invT;
+      if (need_poly) {
+        cpR[s] = a1 + T * (c[C_CP] + T * (c[C_CP + 1] + T * (c[C_CP + 2] + T * c[C_CP + 3])));
+        hRT[s] = a1 + T * (c[C_H] + T * (c[C_H + 1] + T * (c[C_H + 2] + T * c[C_H + 3]))) + a6 * invT;
+      }
+      if constexpr (MLP) {
+        const int ke = kk[s] < n_s ? kk[s] : n_s - 1;
+        const R cn = R(mout[gi * a.mlp.L.nop + ke]);
+        const R hn = R(mout[gi * a.mlp.L.nop + n_s + ke]) * invT;
+        cpR[s] = use_net ? cn : cpR[s];
+        hRT[s] = use_net ? hn : hRT[s];
+      }
       if (mixed) {
         sGb[crow[s]] = a1 * (R(1) - lnT) +
                        T * (c[C_G] + T * (c[C_G + 1] + T * (c[C_G + 2] + T * c[C_G + 3]))) +
@@ -453,23 +492,36 @@ stev_persistent(const KArgs a) {
     t = commit ? t + h : t;
     it += commit ? 1 : 0;
 
-    // ring, DFT and rOF (Eqs 8-13)
+    // ring, DFT and rOF (Eqs 8-13).  Slots are relative to the cell's own
+    // samples, so a cell's arithmetic never depends on where it ran.
     if (a.dft_on) {
       R x[RRPL];
 #pragma unroll
       for (int r = 0; r < RRPL; ++r) x[r] = q[r] * hR;
-      switch (slot) {
+      if constexpr (G == 64) {   // one cell per wave: the slot is wave-uniform
+        if (commit) {
+          switch (__builtin_amdgcn_readfirstlane(rs)) {
 #define STEV_RING_WRITE(M) \
   case M:                  \
     _Pragma("unroll") for (int r = 0; r < RRPL; ++r) ring[r][M] = x[r]; \
     break;
-        STEV_RING_WRITE(0) STEV_RING_WRITE(1) STEV_RING_WRITE(2) STEV_RING_WRITE(3)
-        STEV_RING_WRITE(4) STEV_RING_WRITE(5) STEV_RING_WRITE(6) STEV_RING_WRITE(7)
-        STEV_RING_WRITE(8) STEV_RING_WRITE(9) STEV_RING_WRITE(10) STEV_RING_WRITE(11)
-        STEV_RING_WRITE(12)
+            STEV_RING_WRITE(0) STEV_RING_WRITE(1) STEV_RING_WRITE(2) STEV_RING_WRITE(3)
+            STEV_RING_WRITE(4) STEV_RING_WRITE(5) STEV_RING_WRITE(6) STEV_RING_WRITE(7)
+            STEV_RING_WRITE(8) STEV_RING_WRITE(9) STEV_RING_WRITE(10) STEV_RING_WRITE(11)
+            STEV_RING_WRITE(12)
 #undef STEV_RING_WRITE
-        default: break;
+            default: break;
+          }
+        }
+      } else {                   // several cells per wave: predicated writes
+#pragma unroll
+        for (int m = 0; m < kWin; ++m) {
+          const bool w = commit && rs == m;
+#pragma unroll
+          for (int r = 0; r < RRPL; ++r) ring[r][m] = w ? x[r] : ring[r][m];
+        }
       }
+      rs = commit ? (rs == kWin - 1 ? 0 : rs + 1) : rs;
       const bool full = commit && it >= kWin;
 #pragma unroll
       for (int r = 0; r < RRPL; ++r) {
@@ -497,7 +549,6 @@ stev_persistent(const KArgs a) {
         rOF[r] = (full && jrev[r]) ? upd : rOF[r];
       }
     }
-    slot = (slot == kWin - 1) ? 0 : slot + 1;
   }
 
   // flush statistics: one atomic per wave and counter
@@ -533,7 +584,9 @@ __global__ void stev_zero_u64(unsigned long long *p, int n) {
 namespace stev {
 
 #define STEV_INST(R, G, RPL, RRPL, SPL, CSRR) \
-  reinterpret_cast<const void *>(&stev_persistent<R, G, RPL, RRPL, SPL, CSRR>)
+  reinterpret_cast<const void *>(&stev_persistent<R, G, RPL, RRPL, SPL, CSRR, false>)
+#define STEV_INST_MLP(G, RPL, RRPL, SPL, CSRR) \
+  reinterpret_cast<const void *>(&stev_persistent<float, G, RPL, RRPL, SPL, CSRR, true>)
 
 const VariantInfo kVariants[] = {
 #define STEV_VARIANT(G, RPL, RRPL, SPL, CSRR)                               \
@@ -543,6 +596,13 @@ const VariantInfo kVariants[] = {
 #undef STEV_VARIANT
 };
 const int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
+
+// FP32 state with the thermo network (cp, h from BF16 MFMA inference)
+const void *const kMlpVariants[] = {
+#define STEV_VARIANT(G, RPL, RRPL, SPL, CSRR) STEV_INST_MLP(G, RPL, RRPL, SPL, CSRR),
+    STEV_VARIANT_LIST
+#undef STEV_VARIANT
+};
 const void *kZeroKernel = reinterpret_cast<const void *>(&stev_zero_u64);
 
 }  // namespace stev

@@ -2,9 +2,6 @@
 // clear error until then.
 #include "stev_runtime.h"
 
-void mlp_release(stev_ctx *, stev_mech *) {}
-const void *mlp_kernel_for(int, int) { return nullptr; }
-int mlp_wave_bytes(const stev_mech *, const stev_params &, int) { return 0; }
 void serve_stop(stev_ctx *) {}
 
 extern "C" int stev_integrate_batched(stev_ctx *ctx, int32_t, const stev_mech *const *,
@@ -21,17 +18,6 @@ extern "C" int stev_submit(stev_ctx *ctx, const stev_mech *, int64_t, void *, co
 }
 extern "C" int stev_poll(stev_ctx *ctx, uint64_t, stev_stats *) {
   return stev_fail(ctx, STEV_ENOTFOUND, "stev_poll: not built yet");
-}
-extern "C" int stev_train_thermo_mlp(stev_ctx *ctx, stev_mech *, const stev_mlp_cfg *,
-                                     stev_mlp_report *) {
-  return stev_fail(ctx, STEV_EINVAL, "stev_train_thermo_mlp: not built yet");
-}
-extern "C" int stev_get_thermo_mlp(stev_ctx *ctx, const stev_mech *, float *, int64_t *) {
-  return stev_fail(ctx, STEV_EINVAL, "not built yet");
-}
-extern "C" int stev_set_thermo_mlp(stev_ctx *ctx, stev_mech *, int32_t, double, double,
-                                   const float *, int64_t) {
-  return stev_fail(ctx, STEV_EINVAL, "not built yet");
 }
 extern "C" int stev_autotune(stev_ctx *ctx, const stev_mech *, int64_t, const void *, const void *,
                              const void *, int64_t, int64_t, double, stev_params *) {

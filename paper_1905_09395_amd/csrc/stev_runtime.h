@@ -36,16 +36,14 @@ struct RxnPacked {
   bool zero_order_rev = false;         // a participant without rate-law slot
 };
 
-// thermo network attached to a mechanism
+// thermo network attached to a mechanism (host copy of the FP32 weights)
 struct MlpHost {
   int enabled = 0;
   int hidden = 0;
   double T_lo = 300, T_hi = 3000;
-  std::vector<float> master;        // FP32 weights (export layout) + z-score constants
-  void *dev = nullptr;              // one device buffer holding every array below
+  std::vector<float> master, mean, sd;
+  void *dev = nullptr;              // inference blob (see stev::MlpBlobLayout)
   size_t dev_bytes = 0;
-  stev::MlpDev devv{};
-  stev::MlpDev &dev_view() { return devv; }
 };
 
 struct stev_mech {
@@ -66,7 +64,7 @@ struct stev_mech {
 };
 
 struct LaunchPlan {
-  int variant = -1, G = 1, waves = 8, block = 512, grid = 1, lds = 0, wave_bytes = 0;
+  int variant = -1, G = 1, waves = 8, block = 512, grid = 1, lds = 0, wave_bytes = 0, exch_bytes = 0;
   int occ = 1, compact = 1;
   const void *fn = nullptr;
 };
@@ -107,7 +105,6 @@ int launch_stev(stev_ctx *ctx, const LaunchPlan &lp, stev::KArgs &a, hipStream_t
 
 // thermo network (stev_mlp.hip)
 void mlp_release(stev_ctx *ctx, stev_mech *m);
-const void *mlp_kernel_for(int variant, int precision);
 int mlp_wave_bytes(const stev_mech *m, const stev_params &p, int G);
 
 // serving (stev_serve.hip)

@@ -592,14 +592,16 @@ int plan_launch(stev_ctx *ctx, const stev_mech *m, const stev_params &p, long lo
   lp.G = V.G;
   lp.fn = p.precision == STEV_F64 ? V.fn_f64 : V.fn_f32;
   if (p.thermo == STEV_THERMO_MLP) {
-    lp.fn = mlp_kernel_for(v, p.precision);
-    if (!lp.fn) return stev_fail(ctx, STEV_EINVAL, "no MLP kernel for this variant");
+    if (p.precision != STEV_F32)
+      return stev_fail(ctx, STEV_EINVAL, "the thermo network runs with FP32 state (precision=STEV_F32)");
+    lp.fn = kMlpVariants[v];
   }
   const int rsz = p.precision == STEV_F64 ? 8 : 4;
   const int cpw = 64 / V.G;
-  lp.wave_bytes = align16((m->n_s + 2 + m->n_r + 2 + (m->mixed_tmid ? m->n_s + 2 : 0)) * cpw * rsz) +
-                  mlp_wave_bytes(m, p, V.G);
-  const int mech_bytes = m->L[p.precision].bytes;
+  lp.exch_bytes = align16((m->n_s + 2 + m->n_r + 2 + (m->mixed_tmid ? m->n_s + 2 : 0)) * cpw * rsz);
+  lp.wave_bytes = lp.exch_bytes + mlp_wave_bytes(m, p, V.G);
+  const int mech_bytes = m->L[p.precision].bytes +
+                         (p.thermo == STEV_THERMO_MLP ? m->mlp.dev.L.bytes : 0);
   int waves = p.waves_per_wg > 0 ? p.waves_per_wg : 4;
   while (waves > 1 && mech_bytes + waves * lp.wave_bytes > ctx->max_lds) --waves;
   lp.lds = mech_bytes + waves * lp.wave_bytes;
@@ -632,6 +634,8 @@ int launch_zero(stev_ctx *ctx, unsigned long long *p, int n, hipStream_t s) {
 
 int launch_stev(stev_ctx *ctx, const LaunchPlan &lp, KArgs &a, hipStream_t s) {
   a.wave_bytes = lp.wave_bytes;
+  a.exch_bytes = lp.exch_bytes;
+  a.lds_mech_bytes = a.L.bytes + (a.mlp.enabled ? a.mlp.L.bytes : 0);
   void *args[] = {&a};
   HIP_TRY(hipLaunchKernel(lp.fn, dim3(lp.grid), dim3(lp.block), args, lp.lds, s));
   return STEV_OK;

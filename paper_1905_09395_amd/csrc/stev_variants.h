@@ -23,6 +23,7 @@ struct VariantInfo {
 };
 
 extern const VariantInfo kVariants[];
+extern const void *const kMlpVariants[];   // same order; FP32 + thermo network
 extern const int kNumVariants;
 extern const void *kZeroKernel;
 

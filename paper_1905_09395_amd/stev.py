@@ -115,6 +115,8 @@ def load():
     L.stev_get_thermo_mlp.argtypes = [vp, vp, vp, C.POINTER(i64)]
     L.stev_set_thermo_mlp.argtypes = [vp, vp, i32, dbl, dbl, vp, i64]
     L.stev_autotune.argtypes = [vp, vp, i64, vp, vp, vp, i64, i64, dbl, C.POINTER(Params)]
+    L.stev_mlp_loss_grad.argtypes = [vp, i32, i32, vp, i64, vp, vp, vp, C.POINTER(dbl)]
+    L.stev_thermo_eval.argtypes = [vp, vp, i32, i64, vp, vp, vp]
     L.stev_model_flops.argtypes = [vp, i32, C.POINTER(dbl)]
     L.stev_model_flops.restype = dbl
     L.stev_destroy_mechanism.argtypes = [vp, vp]
@@ -304,6 +306,27 @@ class Context:
         v = np.ascontiguousarray(values, dtype=np.float32)
         self._check(self.lib.stev_set_thermo_mlp(self.h, mech.h, int(hidden), float(T_lo),
                                                  float(T_hi), v.ctypes.data, len(v)))
+
+    def mlp_loss_grad(self, n_out, params, x, target, hidden=32):
+        """GPU loss and gradient of a thermo network (FP32), host arrays."""
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        xx = np.ascontiguousarray(x, dtype=np.float32)
+        t = np.ascontiguousarray(target, dtype=np.float32)
+        g = np.zeros_like(p)
+        loss = C.c_double()
+        self._check(self.lib.stev_mlp_loss_grad(self.h, hidden, n_out, p.ctypes.data, len(xx),
+                                                xx.ctypes.data, t.ctypes.data, g.ctypes.data,
+                                                C.byref(loss)))
+        return loss.value, g
+
+    def thermo_eval(self, mech, T, thermo=THERMO_POLY):
+        """cp/R and h/R at temperatures T ([n, n_s] each), evaluated on the GPU."""
+        TT = np.ascontiguousarray(T, dtype=np.float64)
+        cp = np.zeros((len(TT), mech.n_s))
+        h = np.zeros((len(TT), mech.n_s))
+        self._check(self.lib.stev_thermo_eval(self.h, mech.h, thermo, len(TT), TT.ctypes.data,
+                                              cp.ctypes.data, h.ctypes.data))
+        return cp, h
 
     def autotune(self, mech, T, P, Y, dt_flow, params=None):
         params = params or default_params()

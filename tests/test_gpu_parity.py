@@ -167,3 +167,24 @@ def test_mech19_full_size_sampled(ctx, m19):
         o = oracle_ensemble(om, T[idx], P[idx], Y[idx], DT, prec)
         gs = {k: (v[idx] if isinstance(v, np.ndarray) else v) for k, v in g.items()}
         judge(gs, o, prec, f"full/{prec}")
+
+
+@pytest.mark.parametrize("prec", [stev.F64, stev.F32])
+def test_results_independent_of_launch_shape(ctx, m19, m6, prec):
+    """A cell's result is a function of the cell alone: launch shape, the
+    variant's cell-to-wave packing and the cell's position in the field do
+    not change a single bit."""
+    for (m, gm, om), G in ((m19, 16), (m19, 64), (m6, 1)):
+        T, P, Y = (synth.make_cells_mech19(300, seed=41) if gm is m19[1]
+                   else synth.make_cells_mech6(300, seed=41))
+        say(f"determinism G={G} prec={prec}")
+        a = run_gpu(ctx, gm, T, P, Y, DT, prec, lanes_per_cell=G)
+        b = run_gpu(ctx, gm, T, P, Y, DT, prec, lanes_per_cell=G, waves_per_wg=1, grid_wgs=7,
+                    compact_every=5)
+        # the same cells embedded at other positions of a larger field
+        T2, P2, Y2 = np.concatenate([T[150:], T, T[:150]]), np.concatenate([P[150:], P, P[:150]]), \
+            np.concatenate([Y[150:], Y, Y[:150]])
+        c = run_gpu(ctx, gm, T2, P2, Y2, DT, prec, lanes_per_cell=G)
+        for r in (b, {k: (v[150:450] if isinstance(v, np.ndarray) else v) for k, v in c.items()}):
+            assert np.array_equal(a["T"], r["T"]) and np.array_equal(a["Y"], r["Y"])
+            assert np.array_equal(a["iters"], r["iters"])

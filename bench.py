@@ -1,13 +1,27 @@
 """Benchmark: cells per second over one flow time step on one MI355X.
 
-Workload (default): the synthetic 19-species / 50-reversible-reaction field of
-262 144 cells (70 % at T ~ U[300, 900] K, 30 % at T ~ U[1400, 2500] K,
-Dirichlet mass fractions, 1 atm), integrated over dt_flow = 1e-4 s in FP64.
-A step is one stev_integrate call over the whole field (inputs already
-resident in HBM); before each step the initial state is restored on the
-device.  Prints one JSON line.
+Workload (default, --workload plain): the synthetic 19-species /
+50-reversible-reaction field of 262 144 cells (70 % at T ~ U[300, 900] K,
+30 % at T ~ U[1400, 2500] K, Dirichlet mass fractions, 1 atm), integrated
+over dt_flow = 1e-4 s in FP64.  A step is one stev_integrate call over the
+whole field (inputs already resident in HBM); before each step the initial
+state is restored on the device.  Prints one JSON line.
+
+Other workloads (one JSON line each, same keys):
+  --workload batched  64 batches, log-uniform sizes in [256, 131072],
+                      alternating 6- and 19-species mechanisms, FP32, one
+                      stev_integrate_batched call per step (graph replay,
+                      autotuned launch shape), against 64 plain calls
+  --workload mlp      19 species, 1 048 576 cells, FP32 with the thermo
+                      network against FP32 polynomials
+  --workload serve    Poisson arrivals of requests of log-uniform size in
+                      [1024, 524288] cells over 6-, 19- and 53-species
+                      mechanisms, FP32 + thermo network, host-resident
+                      requests admitted by an HBM budget that binds; p50/p99
+                      latency against plain per-request launches
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision f64|f32]
+                  [--workload plain|batched|mlp|serve]
 """
 
 import argparse
@@ -88,6 +102,305 @@ def cpu_baseline(mech, T, P, Y, dt, budget_s=12.0):
                       f"FP64 oracle time with OpenMP over {cores} host threads"}
 
 
+def base_record(args, value, el, dtype, workload, **config):
+    return {"metric": METRIC, "value": value, "unit": "cells/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": el * 1e3 / args.steps,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": dtype,
+            "data": "synthetic", "config": dict(workload=workload, **config)}
+
+
+def run_batched(args):
+    """64 uneven batches per step in one stev_integrate_batched call."""
+    import numpy as np
+    import torch
+
+    from paper_1905_09395_amd import stev, synth
+    dev = torch.device("cuda:0")
+    dt = 1e-4
+    batches = synth.make_batches(64, 256, 131072, seed=103)
+    ctx = stev.Context(0)
+    ctx.set_stream(torch.cuda.current_stream(dev))
+    mechs = {6: ctx.mechanism(synth.make_mech6()), 19: ctx.mechanism(synth.make_mech19())}
+    prec = stev.F32
+    f32 = torch.float32
+    B = [dict(key=k, T0=torch.tensor(T, dtype=f32, device=dev),
+              P=torch.tensor(P, dtype=f32, device=dev),
+              Y0=torch.tensor(Y, dtype=f32, device=dev).contiguous(),
+              it=torch.zeros(len(T), dtype=torch.int32, device=dev)) for k, T, P, Y in batches]
+    for b in B:
+        b["T"], b["Y"] = b["T0"].clone(), b["Y0"].clone()
+    n_cells = sum(len(b[1]) for b in batches)
+    # autotuned launch shape per mechanism (on that mechanism's cells), outside
+    # the timed region
+    tuned = {}
+    for k, gm in mechs.items():
+        sel = [b for b in B if b["key"] == k]
+        Tc = torch.cat([b["T0"] for b in sel])
+        Pc = torch.cat([b["P"] for b in sel])
+        Yc = torch.cat([b["Y0"] for b in sel])
+        tuned[k] = ctx.autotune(gm, Tc, Pc, Yc, dt, stev.default_params(precision=prec))
+    # one set of launch parameters serves the call: the larger mechanism's
+    prm = tuned[19]
+
+    def restore():
+        for b in B:
+            b["T"].copy_(b["T0"])
+            b["Y"].copy_(b["Y0"])
+
+    def step_batched():
+        restore()
+        return ctx.integrate_batched([mechs[b["key"]] for b in B], [b["T"] for b in B],
+                                     [b["P"] for b in B], [b["Y"] for b in B], dt, params=prm,
+                                     iters=[b["it"] for b in B])[1]
+
+    def step_plain():
+        restore()
+        ms = 0.0
+        for b in B:
+            ms += ctx.integrate(mechs[b["key"]], b["T"], b["P"], b["Y"], dt,
+                                params=stev.default_params(precision=prec))[1]["kernel_ms"]
+        return ms
+
+    for _ in range(args.warmup):
+        step_batched()
+        step_plain()
+    torch.cuda.synchronize()
+    # per-mechanism iteration totals (deterministic) for the model FLOPs
+    step_batched()
+    torch.cuda.synchronize()
+    work = 0.0
+    for k, gm in mechs.items():
+        its = sum(int(b["it"].sum().item()) for b in B if b["key"] == k)
+        work += its * gm.model_flops(stev.THERMO_POLY)[0]
+    t0 = time.perf_counter()
+    kms = []
+    for _ in range(args.steps):
+        kms.append(step_batched()["kernel_ms"])
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    t1 = time.perf_counter()
+    pms = []
+    for _ in range(args.steps):
+        pms.append(step_plain())
+    torch.cuda.synchronize()
+    el_plain = time.perf_counter() - t1
+    k_ms = float(np.mean(kms))
+    achieved = work / (k_ms * 1e-3) / 1e12
+    out = base_record(args, n_cells * args.steps / el, el, "f32",
+                      "batched STEV: 64 batches of log-uniform size in [256, 131072], "
+                      "alternating 6-species/4-reaction and 19-species/50-reaction "
+                      "mechanisms, one persistent launch per mechanism, graph replay, "
+                      "autotuned launch shape, FP32, dt_flow=1e-4 s",
+                      cells=n_cells, batches=64,
+                      tuned={str(k): dict(lanes_per_cell=v.lanes_per_cell,
+                                          waves_per_wg=v.waves_per_wg,
+                                          compact_every=v.compact_every)
+                             for k, v in tuned.items()},
+                      plain_per_batch_cells_per_s=n_cells * args.steps / el_plain,
+                      plain_per_batch_kernel_ms=float(np.mean(pms)),
+                      speedup_vs_plain_per_batch=el_plain / el)
+    out["roofline"] = {"bound": "alu", "achieved": achieved, "peak": PEAK["f32"],
+                       "unit": "TFLOP/s", "frac": achieved / PEAK["f32"], "traffic": None,
+                       "kernel_ms": k_ms}
+    ctx.close()
+    return out
+
+
+def run_mlp(args):
+    """1 048 576 cells of the 19-species field, FP32, thermo network vs polynomials."""
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_1905_09395_amd import stev, synth
+    dev = torch.device("cuda:0")
+    dt = 1e-4
+    n = 1 << 20
+    mech = synth.make_mech19()
+    T, P, Y = synth.make_cells_mech19(n, seed=104)
+    ctx = stev.Context(0)
+    ctx.set_stream(torch.cuda.current_stream(dev))
+    gm = ctx.mechanism(mech)
+    rep = ctx.train_thermo_mlp(gm, epochs=300, n_samples=1 << 20, batch=8192, lr=3e-3, seed=104)
+    f32 = torch.float32
+    T0 = torch.tensor(T, dtype=f32, device=dev)
+    P0 = torch.tensor(P, dtype=f32, device=dev)
+    Y0 = torch.tensor(Y, dtype=f32, device=dev).contiguous()
+    Tw, Yw = T0.clone(), Y0.clone()
+    res = {}
+    for name, th in (("network", stev.THERMO_MLP), ("poly", stev.THERMO_POLY)):
+        prm = stev.default_params(precision=stev.F32, thermo=th)
+        for _ in range(args.warmup):
+            Tw.copy_(T0); Yw.copy_(Y0)
+            ctx.integrate(gm, Tw, P0, Yw, dt, params=prm)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        kms, its = [], []
+        for _ in range(args.steps):
+            Tw.copy_(T0); Yw.copy_(Y0)
+            st = ctx.integrate(gm, Tw, P0, Yw, dt, params=prm)[1]
+            kms.append(st["kernel_ms"]); its.append(st["total_iters"])
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        # accuracy on a seeded subsample against the FP64 oracle
+        idx = synth.subsample(n, 256, seed=4)
+        o = oracle.integrate(oracle.OracleMech(mech), T[idx], P[idx], Y[idx], dt)
+        gT = Tw.cpu().double().numpy()[idx]
+        gY = Yw.cpu().double().numpy()[idx]
+        m = o["Y"] > 1e-6
+        relT = np.abs(gT - o["T"]) / o["T"]
+        relY = np.where(m, np.abs(gY - o["Y"]) / np.where(m, o["Y"], 1), 0).max(axis=1)
+        res[name] = dict(el=el, kms=float(np.mean(kms)), its=float(np.mean(its)),
+                         median_rel_T=float(np.median(relT)), p99_rel_T=float(np.quantile(relT, .99)),
+                         median_rel_Y=float(np.median(relY)), p99_rel_Y=float(np.quantile(relY, .99)))
+    flops = gm.model_flops(stev.THERMO_POLY)[0]
+    r = res["network"]
+    achieved = r["its"] * flops / (r["kms"] * 1e-3) / 1e12
+    out = base_record(args, n * args.steps / r["el"], r["el"], "f32",
+                      "learned thermo: 19-species/50-reaction mechanism, 1048576 cells, FP32, "
+                      "cp and h from a 1-32-32-38 tanh network (bf16 MFMA, fp32 accumulation, "
+                      "polynomial fallback outside 300-3000 K), dt_flow=1e-4 s",
+                      cells=n, network_train=dict(test_loss=rep["test_loss"],
+                                                  max_rel_err_cp=rep["max_rel_err_cp"],
+                                                  max_rel_err_h=rep["max_rel_err_h"],
+                                                  train_ms=rep["train_ms"]),
+                      network=dict((k, v) for k, v in r.items() if k != "el"),
+                      polynomials=dict((k, v) for k, v in res["poly"].items() if k != "el"),
+                      poly_cells_per_s=n * args.steps / res["poly"]["el"],
+                      network_over_poly_time=r["el"] / res["poly"]["el"],
+                      accuracy_sample="256 seeded cells vs the FP64 oracle; relative errors, "
+                                      "Y over Y_k > 1e-6")
+    out["roofline"] = {"bound": "alu", "achieved": achieved, "peak": PEAK["f32"],
+                       "unit": "TFLOP/s", "frac": achieved / PEAK["f32"], "traffic": None,
+                       "kernel_ms": r["kms"]}
+    ctx.close()
+    return out
+
+
+def run_serve(args):
+    """Poisson-arrival serving against plain per-request launches."""
+    import threading
+
+    import numpy as np
+    import torch
+
+    from paper_1905_09395_amd import stev, synth
+    dt = 1e-4
+    rng = np.random.default_rng(105)
+    n_req = 40
+    sizes = np.round(np.exp(rng.uniform(np.log(1024), np.log(524288), n_req))).astype(int)
+    keys = rng.choice([6, 19, 53], n_req)
+    mean_cells = 83879.0
+    src = {6: synth.make_mech6(), 19: synth.make_mech19(), 53: synth.make_mech53()}
+    # host-resident (pinned) request state staged through a device budget of
+    # 512 MiB, which the larger requests in flight together exceed
+    budget = 512 << 20
+    ctx = stev.Context(0, hbm_budget=budget)
+    mechs = {k: ctx.mechanism(m) for k, m in src.items()}
+    for k, gm in mechs.items():
+        ctx.train_thermo_mlp(gm, epochs=100, n_samples=1 << 20, batch=4096, lr=3e-3, seed=104)
+    prm = stev.default_params(precision=stev.F32, thermo=stev.THERMO_MLP)
+
+    def make(k, n, seed):
+        T, P, Y = synth.make_cells_mech6(n, seed) if k == 6 else synth.make_cells_split(n, k, seed)
+        pin = lambda a: torch.tensor(a, dtype=torch.float32).pin_memory()
+        return dict(k=int(k), T0=pin(T), P=pin(P), Y0=pin(Y), T=pin(T), Y=pin(Y))
+
+    reqs = [make(k, n, 50000 + i) for i, (k, n) in enumerate(zip(keys, sizes))]
+    total = int(sizes.sum())
+
+    def reset():
+        for r in reqs:
+            r["T"].copy_(r["T0"]); r["Y"].copy_(r["Y0"])
+
+    # capacity: plain per-request launches back to back
+    reset()
+    t0 = time.perf_counter()
+    for r in reqs:
+        ctx.integrate(mechs[r["k"]], r["T"], r["P"], r["Y"], dt, params=prm)
+    cap = total / (time.perf_counter() - t0)
+
+    def arrivals(load):
+        lam = load * cap / mean_cells
+        return np.cumsum(np.random.default_rng(7).exponential(1.0 / lam, n_req))
+
+    def serve_run(at):
+        import queue
+        reset()
+        lat = [None] * n_req
+        waits = [0] * n_req
+        submitted = queue.Queue()
+        start = time.perf_counter()
+
+        def submitter():
+            for i, r in enumerate(reqs):
+                d = at[i] - (time.perf_counter() - start)
+                if d > 0:
+                    time.sleep(d)
+                submitted.put((ctx.submit(mechs[r["k"]], r["T"], r["P"], r["Y"], dt,
+                                          params=prm), i))
+
+        th = threading.Thread(target=submitter)
+        th.start()
+        pending = {}
+        n_done = 0
+        while n_done < n_req:
+            while not submitted.empty():
+                tk, i = submitted.get()
+                pending[tk] = i
+            for tk in list(pending):
+                rc, st = ctx.poll(tk)
+                if rc != stev.STEV_EAGAIN:
+                    i = pending.pop(tk)
+                    lat[i] = (time.perf_counter() - start) - at[i]
+                    waits[i] = st["budget_waits"]
+                    n_done += 1
+            time.sleep(1e-4)
+        th.join()
+        makespan = time.perf_counter() - start
+        return np.array(lat), makespan, int(np.sum(np.array(waits) > 0))
+
+    def plain_run(at):
+        reset()
+        lat = np.zeros(n_req)
+        start = time.perf_counter()
+        for i, r in enumerate(reqs):
+            d = at[i] - (time.perf_counter() - start)
+            if d > 0:
+                time.sleep(d)
+            ctx.integrate(mechs[r["k"]], r["T"], r["P"], r["Y"], dt, params=prm)
+            lat[i] = (time.perf_counter() - start) - at[i]
+        return lat, time.perf_counter() - start
+
+    rows = {}
+    for load in (0.5, 0.8, 0.95):
+        at = arrivals(load)
+        for _ in range(args.warmup):
+            serve_run(at)
+        ls, ms, bw = [], [], []
+        for _ in range(args.steps):
+            l, m, w = serve_run(at)
+            ls.append(l); ms.append(m); bw.append(w)
+        lp, mp = plain_run(at)
+        L = np.concatenate(ls)
+        rows[str(load)] = dict(
+            serve_p50_ms=1e3 * float(np.quantile(L, .5)), serve_p99_ms=1e3 * float(np.quantile(L, .99)),
+            serve_cells_per_s=total / float(np.mean(ms)),
+            requests_that_waited_for_budget=int(np.max(bw)),
+            plain_p50_ms=1e3 * float(np.quantile(lp, .5)), plain_p99_ms=1e3 * float(np.quantile(lp, .99)),
+            plain_cells_per_s=total / mp)
+    top = rows["0.95"]
+    out = base_record(args, top["serve_cells_per_s"], float(np.sum(ms)), "f32",
+                      "serving: Poisson arrivals, 40 requests of log-uniform size in "
+                      "[1024, 524288] cells over 6-, 19- and 53-species mechanisms, FP32 + "
+                      "thermo network, host-resident pinned requests admitted by a 512 MiB HBM "
+                      "budget; value at load 0.95",
+                      requests=n_req, cells=total, hbm_budget_bytes=budget,
+                      plain_capacity_cells_per_s=cap, loads=rows)
+    ctx.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -99,6 +412,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--probe", action="store_true",
                     help="counter-calibration run: one plain copy, then one step")
+    ap.add_argument("--workload", default="plain", choices=["plain", "batched", "mlp", "serve"])
     args = ap.parse_args()
     if args.probe:
         args.steps, args.warmup, args.no_cpu = 1, 0, True
@@ -113,6 +427,10 @@ def main():
     from paper_1905_09395_amd import stev, synth
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.workload != "plain":
+        out = {"batched": run_batched, "mlp": run_mlp, "serve": run_serve}[args.workload](args)
+        print(json.dumps(out), flush=True)
+        return
     dev = torch.device("cuda:0")
     if args.probe:
         traffic_probe(args.precision)

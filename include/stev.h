@@ -80,10 +80,12 @@ typedef struct {
   int32_t dft_window;     /* Eq 8 ring length: 13, or 0 to disable  (13)   */
   int32_t lanes_per_cell; /* 0 auto, else 1|8|16|32|64                      */
   int64_t max_iters;      /* per-cell iteration cap -> status 2     (1e6)  */
-  int32_t waves_per_wg;   /* 0 auto (1..16)                                  */
+  int32_t waves_per_wg;   /* 0 auto, else 1..4 waves per workgroup          */
   int32_t compact_every;  /* refill cadence K in iterations, 0 auto (1)     */
   int32_t grid_wgs;       /* persistent workgroups, 0 auto                  */
-  int32_t reserved;
+  int32_t use_graph;      /* stev_integrate_batched: record the launch
+                             sequence as a HIP graph and replay it when an
+                             identical call repeats (1), or launch directly (0) */
 } stev_params;
 
 /* Per-call statistics. */
@@ -99,6 +101,9 @@ typedef struct {
   int32_t grid_wgs;
   int32_t compact_every;
   double latency_ms;      /* serving: submit -> completion observed */
+  double queued_ms;       /* serving: submit -> admission (launch) */
+  int32_t budget_waits;   /* serving: admission attempts refused for lack of HBM budget */
+  int32_t round_requests; /* serving: requests that shared this request's launch */
 } stev_stats;
 
 void stev_default_params(stev_params *p);
@@ -130,10 +135,20 @@ int stev_integrate(stev_ctx *ctx, const stev_mech *mech, int64_t n_cells,
                    int64_t ld_species, double dt_flow, const stev_params *params,
                    int32_t *iters_out, uint8_t *status_out, stev_stats *stats);
 
-/* Many independent cell batches (possibly different mechanisms) in one
- * persistent launch per mechanism group.  Arrays of length n_batches; every
- * batch uses `params` (its precision selects the pointer types).  Device
- * pointers only.  iters_out/status_out entries may be NULL. */
+/* Many independent cell batches (Sec 2.4 variable loading over all of them):
+ * one persistent launch per distinct mechanism, whose global cell counter
+ * runs over the concatenation of that mechanism's batches, so uneven batch
+ * sizes balance themselves; launches for different mechanisms overlap on
+ * side streams.  Arrays have length n_batches; batch b follows the layout
+ * rules of stev_integrate with its own T[b], P[b], Y[b], ld_cell[b],
+ * ld_species[b], iters_out[b], status_out[b] (the last two arrays and their
+ * entries may be NULL).  Device pointers only.  Every batch uses `params`
+ * (its precision selects the pointer types).  With params->use_graph the
+ * launch sequence is recorded as a HIP graph on first use and replayed when
+ * the same call (same pointers, sizes, mechanisms and parameters) repeats;
+ * up to 8 such sequences are kept per context.  stats aggregates all
+ * batches; kernel_ms covers the whole sequence.  Blocking.  Returns
+ * STEV_ECELLS if any cell failed. */
 int stev_integrate_batched(stev_ctx *ctx, int32_t n_batches, const stev_mech *const *mechs,
                            const int64_t *n_cells, void *const *T, const void *const *P,
                            void *const *Y, const int64_t *ld_cell, const int64_t *ld_species,
@@ -208,10 +223,15 @@ int stev_mlp_loss_grad(stev_ctx *ctx, int32_t hidden, int32_t n_out, const float
 int stev_thermo_eval(stev_ctx *ctx, const stev_mech *mech, int32_t thermo, int64_t n,
                      const double *T, double *cp_R, double *h_R);
 
-/* Pick lanes_per_cell, waves_per_wg and compact_every by timing trial runs
- * on a private copy of up to n_cells_hint synthetic cells drawn from the
- * given device state (read-only).  Results are written to *inout and cached
- * per (mechanism shape, precision, thermo, size bucket). */
+/* Pick lanes_per_cell (cells per wavefront / workgroup), waves_per_wg and
+ * compact_every (refill cadence, Sec 2.4) by timing trial integrations of a
+ * private copy of the given cells (the first min(n_cells, 2^20); host or
+ * device pointers, read-only; Y cell-major with ld_species == 1 or
+ * species-major with ld_cell == 1).  Only the fields that are 0 (auto) in
+ * *inout are tuned; the others are kept and the result is written back into
+ * *inout.  Results are cached per context by (mechanism shape, precision,
+ * thermo, dft_window, log2 of n_cells): a cache hit runs nothing.  Results of
+ * an integration do not depend on these fields, only its time does. */
 int stev_autotune(stev_ctx *ctx, const stev_mech *mech, int64_t n_cells, const void *T,
                   const void *P, const void *Y, int64_t ld_cell, int64_t ld_species,
                   double dt_flow, stev_params *inout);

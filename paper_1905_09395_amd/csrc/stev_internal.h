@@ -77,6 +77,19 @@ struct MlpDev {
   MlpBlobLayout L;
 };
 
+// One batch of a multi-batch launch: cells [begin, begin + n) of the launch's
+// global index space live in this batch's own arrays (same layout rules as a
+// single call: T[c], P[c], Y[c*ld_cell + k*ld_sp]).
+struct BatchDesc {
+  long long begin;
+  void *T;
+  const void *P;
+  void *Y;
+  long long ld_cell, ld_sp;
+  int *iters_out;               // nullable
+  unsigned char *status_out;    // nullable
+};
+
 struct KArgs {
   const void *blob;
   MechLayout L;
@@ -99,6 +112,12 @@ struct KArgs {
   int dft_on, compact_every;
   // control: [0] next cell, [1] sum iters, [2] max iters, [3] failed cells
   unsigned long long *ctl;
+  // multi-batch launch: nullptr for one batch given by T..status_out above;
+  // otherwise n_batches descriptors sorted by begin (batches[0].begin = 0),
+  // and per-batch statistics bstats[4b + {0 sum iters, 1 max iters, 2 failed}]
+  const BatchDesc *batches;
+  unsigned long long *bstats;
+  int n_batches;
   MlpDev mlp;
 };
 

@@ -146,6 +146,51 @@ __device__ __forceinline__ R conc_pow(R C, R o, int has_frac) {
   return r;
 }
 
+// Where a cell's state lives: batch b (or -1 for a single-batch launch) and
+// the cell's index c inside it.
+template <typename R>
+struct CellRef {
+  R *T;
+  const R *P;
+  R *Y;              // species 0 of this cell; species k at Y[k * ld_sp]
+  long long ld_sp;
+  int *iters;
+  unsigned char *status;
+};
+
+template <typename R>
+__device__ __forceinline__ CellRef<R> cell_ref(const KArgs &a, int b, long long c) {
+  CellRef<R> r;
+  if (b < 0) {
+    r.T = reinterpret_cast<R *>(a.T) + c;
+    r.P = reinterpret_cast<const R *>(a.P) + c;
+    r.Y = reinterpret_cast<R *>(a.Y) + c * a.ld_cell;
+    r.ld_sp = a.ld_sp;
+    r.iters = a.iters_out ? a.iters_out + c : nullptr;
+    r.status = a.status_out ? a.status_out + c : nullptr;
+  } else {
+    const BatchDesc &d = a.batches[b];
+    r.T = reinterpret_cast<R *>(d.T) + c;
+    r.P = reinterpret_cast<const R *>(d.P) + c;
+    r.Y = reinterpret_cast<R *>(d.Y) + c * d.ld_cell;
+    r.ld_sp = d.ld_sp;
+    r.iters = d.iters_out ? d.iters_out + c : nullptr;
+    r.status = d.status_out ? d.status_out + c : nullptr;
+  }
+  return r;
+}
+
+// Batch holding global cell g: the last descriptor with begin <= g (empty
+// batches share their begin with the next one and are skipped).
+__device__ __forceinline__ int find_batch(const KArgs &a, long long g) {
+  int lo = 0, hi = a.n_batches - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (a.batches[mid].begin <= g) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
 template <typename R, int G, int RPL, int RRPL, int SPL, int CSRR, bool MLP>
 __global__ void __launch_bounds__(256)
 stev_persistent(const KArgs a) {
@@ -237,10 +282,6 @@ stev_persistent(const KArgs a) {
       coff[s][e] = csr_reg ? (o0 | (o1 << 16)) : 0u;
     }
 
-  R *Tg = reinterpret_cast<R *>(a.T);
-  const R *Pg = reinterpret_cast<const R *>(a.P);
-  R *Yg = reinterpret_cast<R *>(a.Y);
-
   const R ystep = R(a.ystep), alpha = R(a.alpha);
   const R tol_ring2 = R(a.tol_ring2), tol_freq = R(a.tol_freq);
   const R r_fac = R(a.r_fac), r_fac_inv = R(a.r_fac_inv), rof_min = R(a.rof_min);
@@ -249,7 +290,8 @@ stev_persistent(const KArgs a) {
   const double tf = a.tf, dtmax = a.dtmax;
 
   // per-cell state (replicated over the group where scalar)
-  long long cell = -1;
+  long long cell = -1;   // index inside batch cb
+  int cb = -1;
   bool active = false, exhausted = false;
   int st = 0;
   int it = 0;
@@ -282,16 +324,23 @@ stev_persistent(const KArgs a) {
     if (__any(fin)) {
       if (fin) {
         if (st == 0 && t < tf) st = 2;
-        if (l == 0) Tg[cell] = T;
+        const CellRef<R> cr = cell_ref<R>(a, cb, cell);
+        if (l == 0) *cr.T = T;
 #pragma unroll
         for (int s = 0; s < SPL; ++s)
-          if (kv[s]) Yg[cell * a.ld_cell + (long long)kk[s] * a.ld_sp] = Y[s];
+          if (kv[s]) cr.Y[(long long)kk[s] * cr.ld_sp] = Y[s];
         if (l == 0) {
-          if (a.iters_out) a.iters_out[cell] = it;
-          if (a.status_out) a.status_out[cell] = (unsigned char)st;
+          if (cr.iters) *cr.iters = it;
+          if (cr.status) *cr.status = (unsigned char)st;
           sum_it += it;
           max_it = it > max_it ? it : max_it;
           n_fail += (st != 0);
+          if (cb >= 0) {
+            unsigned long long *bs = a.bstats + 4 * cb;
+            atomicAdd(&bs[0], (unsigned long long)it);
+            atomicMax(&bs[1], (unsigned long long)it);
+            if (st != 0) atomicAdd(&bs[2], 1ull);
+          }
         }
         active = false;
       }
@@ -309,15 +358,17 @@ stev_persistent(const KArgs a) {
         const unsigned long long below = (gi == 0) ? 0ull : (m & ((1ull << (gi * G)) - 1ull));
         const int rank = __popcll(below);
         if (want) {
-          const long long c = (long long)base + rank;
-          if (c < a.n_cells) {
-            cell = c;
-            T = Tg[c];
-            P = Pg[c];
+          const long long g = (long long)base + rank;
+          if (g < a.n_cells) {
+            cb = a.batches ? find_batch(a, g) : -1;
+            cell = a.batches ? g - a.batches[cb].begin : g;
+            const CellRef<R> cr = cell_ref<R>(a, cb, cell);
+            T = *cr.T;
+            P = *cr.P;
             invP = R(1) / P;
 #pragma unroll
             for (int s = 0; s < SPL; ++s)
-              Y[s] = kv[s] ? Yg[c * a.ld_cell + (long long)kk[s] * a.ld_sp] : R(0);
+              Y[s] = kv[s] ? cr.Y[(long long)kk[s] * cr.ld_sp] : R(0);
 #pragma unroll
             for (int r = 0; r < RRPL; ++r) rOF[r] = R(1);     // Eq 11
             t = 0.0;

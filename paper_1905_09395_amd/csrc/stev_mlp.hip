@@ -420,6 +420,8 @@ int attach_network(stev_ctx *ctx, stev_mech *m, const std::vector<float> &prm,
 
 // ------------------------------- host API --------------------------------
 void mlp_release(stev_ctx *ctx, stev_mech *m) {
+  plans_forget(ctx, m);
+  ++m->version;
   if (m->mlph.dev) dev_free(ctx, m->mlph.dev, m->mlph.dev_bytes);
   m->mlph.dev = nullptr;
   m->mlph.dev_bytes = 0;

@@ -17,6 +17,13 @@
 
 struct stev_ctx;
 
+#define HIP_TRY(expr)                                                              \
+  do {                                                                             \
+    hipError_t e_ = (expr);                                                        \
+    if (e_ != hipSuccess)                                                          \
+      return stev_fail(ctx, STEV_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
 // grow-only device buffer charged to the context's HBM budget
 struct Scratch {
   void *ptr = nullptr;
@@ -48,6 +55,7 @@ struct MlpHost {
 
 struct stev_mech {
   int n_s = 0, n_r = 0, n_rev = 0, max_part = 0, has_frac = 0, mixed_tmid = 0, dmax = 1;
+  uint64_t version = 0;              // bumped when the attached network changes
   std::vector<double> W, nasa_lo, nasa_hi, T_mid;
   std::vector<RxnPacked> rx;        // packed order: reversible first
   std::vector<int> orig_of_new;
@@ -69,6 +77,53 @@ struct LaunchPlan {
   const void *fn = nullptr;
 };
 
+// One batch of a multi-batch launch as the caller described it.
+struct BatchItem {
+  const stev_mech *m = nullptr;
+  long long n = 0;
+  void *T = nullptr;
+  const void *P = nullptr;
+  void *Y = nullptr;
+  long long ld_cell = 0, ld_sp = 0;
+  int32_t *iters = nullptr;
+  uint8_t *status = nullptr;
+};
+
+// Many batches run as one persistent launch per mechanism (stev_batched.hip).
+// Device and pinned host buffers share one layout: the batch descriptors of
+// every group, then per batch 4 statistics words, then per group 8 control
+// words.
+struct MultiLaunch {
+  std::vector<BatchItem> items;
+  stev_params p{};
+  double dt = 0;
+  struct Grp {
+    const stev_mech *m = nullptr;
+    std::vector<int> idx;       // items of this group, in call order
+    long long cells = 0;
+    LaunchPlan lp;
+    stev::KArgs a{};
+  };
+  std::vector<Grp> groups;
+  void *dev = nullptr;
+  void *host = nullptr;
+  size_t bytes = 0, off_stats = 0;
+  // buffers lent by the caller (capacity `cap` each) instead of allocated here
+  bool lent = false;
+  size_t cap = 0;
+  size_t stat_words = 0;        // 4 per item + 8 per group
+  hipGraphExec_t exec = nullptr;
+  std::vector<const stev_mech *> mechs;
+  std::vector<uint64_t> mech_versions;
+  uint64_t last_use = 0;
+};
+
+int ml_build(stev_ctx *ctx, MultiLaunch &ml, hipStream_t s);
+int ml_enqueue(stev_ctx *ctx, MultiLaunch &ml, hipStream_t s, bool fork);
+void ml_read_stats(const MultiLaunch &ml, int item, stev_stats *st);
+void ml_release(stev_ctx *ctx, MultiLaunch &ml);
+void plans_forget(stev_ctx *ctx, const stev_mech *m);
+
 struct ServeState;   // stev_serve.hip
 
 struct stev_ctx {
@@ -88,6 +143,14 @@ struct stev_ctx {
   Scratch sT, sP, sY, sI, sS;
   ServeState *serve = nullptr;
   std::map<std::string, stev_params> tune_cache;
+  // multi-batch launches: side streams for mechanism groups, fork/join events
+  // and the cache of recorded launch sequences (HIP graphs), keyed by call
+  static constexpr int kSide = 3;
+  hipStream_t side[kSide] = {nullptr, nullptr, nullptr};
+  hipEvent_t ev_fork = nullptr;
+  hipEvent_t ev_join[kSide] = {nullptr, nullptr, nullptr};
+  std::map<std::string, MultiLaunch *> plans;
+  uint64_t plan_clock = 0;
 };
 
 int stev_fail(stev_ctx *ctx, int code, const char *fmt, ...);

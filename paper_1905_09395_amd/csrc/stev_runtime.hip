@@ -39,12 +39,6 @@ int stev_fail(stev_ctx *ctx, int code, const char *fmt, ...) {
   return code;
 }
 
-#define HIP_TRY(expr)                                                              \
-  do {                                                                             \
-    hipError_t e_ = (expr);                                                        \
-    if (e_ != hipSuccess)                                                          \
-      return stev_fail(ctx, STEV_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)); \
-  } while (0)
 
 // ---------------------------------------------------------------------------
 // device memory with budget accounting
@@ -126,6 +120,7 @@ extern "C" void stev_default_params(stev_params *p) {
   p->waves_per_wg = 0;
   p->compact_every = 0;
   p->grid_wgs = 0;
+  p->use_graph = 1;
 }
 
 extern "C" int stev_init(stev_ctx **out, int hip_device, size_t hbm_budget_bytes) {
@@ -158,6 +153,14 @@ extern "C" int stev_init(stev_ctx **out, int hip_device, size_t hbm_budget_bytes
   ctx->stream = ctx->own_stream;
   (void)hipEventCreate(&ctx->ev0);
   (void)hipEventCreate(&ctx->ev1);
+  (void)hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming);
+  for (int i = 0; i < stev_ctx::kSide; ++i) {
+    if (hipStreamCreateWithFlags(&ctx->side[i], hipStreamNonBlocking) != hipSuccess) {
+      stev_shutdown(ctx);
+      return STEV_EDEVICE;
+    }
+    (void)hipEventCreateWithFlags(&ctx->ev_join[i], hipEventDisableTiming);
+  }
   if (dev_alloc(ctx, (void **)&ctx->ctl, 64 * sizeof(unsigned long long)) != STEV_OK) {
     stev_shutdown(ctx);
     return STEV_ENOMEM;
@@ -178,7 +181,11 @@ extern "C" int stev_set_stream(stev_ctx *ctx, void *s) {
 
 extern "C" const char *stev_last_error(const stev_ctx *ctx) {
   if (!ctx) return "null context";
-  return ctx->err.c_str();
+  // a copy per calling thread: the serving thread may set the message meanwhile
+  thread_local std::string copy;
+  std::lock_guard<std::mutex> g(const_cast<stev_ctx *>(ctx)->err_mu);
+  copy = ctx->err;
+  return copy.c_str();
 }
 
 extern "C" void stev_shutdown(stev_ctx *ctx) {
@@ -186,6 +193,14 @@ extern "C" void stev_shutdown(stev_ctx *ctx) {
   (void)hipSetDevice(ctx->device);
   serve_stop(ctx);
   if (ctx->own_stream) (void)hipStreamSynchronize(ctx->own_stream);
+  for (int i = 0; i < stev_ctx::kSide; ++i)
+    if (ctx->side[i]) (void)hipStreamSynchronize(ctx->side[i]);
+  plans_forget(ctx, nullptr);
+  for (int i = 0; i < stev_ctx::kSide; ++i) {
+    if (ctx->side[i]) (void)hipStreamDestroy(ctx->side[i]);
+    if (ctx->ev_join[i]) (void)hipEventDestroy(ctx->ev_join[i]);
+  }
+  if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
   for (auto *s : {&ctx->sT, &ctx->sP, &ctx->sY, &ctx->sI, &ctx->sS}) s->release(ctx);
   dev_free(ctx, ctx->ctl, 64 * sizeof(unsigned long long));
   if (ctx->ctl_host) (void)hipHostFree(ctx->ctl_host);
@@ -464,6 +479,7 @@ extern "C" void stev_destroy_mechanism(stev_ctx *ctx, stev_mech *m) {
   if (ctx) {
     (void)hipSetDevice(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
+    plans_forget(ctx, m);
     for (int p = 0; p < 2; ++p) dev_free(ctx, m->blob[p], m->blob_bytes[p]);
     mlp_release(ctx, m);
   }
@@ -610,7 +626,8 @@ int plan_launch(stev_ctx *ctx, const stev_mech *m, const stev_params &p, long lo
                      ctx->max_lds);
   lp.waves = waves;
   lp.block = 64 * waves;
-  hipFuncSetAttribute(lp.fn, hipFuncAttributeMaxDynamicSharedMemorySize, lp.lds);
+  // the attribute is per kernel, shared by every plan that uses it: allow the maximum
+  (void)hipFuncSetAttribute(lp.fn, hipFuncAttributeMaxDynamicSharedMemorySize, ctx->max_lds);
   int occ = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, lp.fn, lp.block, lp.lds) != hipSuccess ||
       occ < 1)

@@ -13,6 +13,7 @@ from __future__ import annotations
 import ctypes as C
 import os
 import re
+import sys
 
 import numpy as np
 
@@ -48,7 +49,7 @@ class Params(C.Structure):
                 ("rof_min", C.c_double), ("dft_window", C.c_int32),
                 ("lanes_per_cell", C.c_int32), ("max_iters", C.c_int64),
                 ("waves_per_wg", C.c_int32), ("compact_every", C.c_int32),
-                ("grid_wgs", C.c_int32), ("reserved", C.c_int32)]
+                ("grid_wgs", C.c_int32), ("use_graph", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -57,7 +58,8 @@ class Stats(C.Structure):
                 ("kernel_ms", C.c_double), ("total_ms", C.c_double),
                 ("lanes_per_cell", C.c_int32), ("waves_per_wg", C.c_int32),
                 ("grid_wgs", C.c_int32), ("compact_every", C.c_int32),
-                ("latency_ms", C.c_double)]
+                ("latency_ms", C.c_double), ("queued_ms", C.c_double),
+                ("budget_waits", C.c_int32), ("round_requests", C.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -139,6 +141,14 @@ def default_params(**kw):
     return p
 
 
+def _after_torch():
+    """Order a library call after the work torch has queued on its current
+    stream (the library runs on its own stream): wait for that stream."""
+    t = sys.modules.get("torch")
+    if t is not None and t.cuda.is_available() and t.cuda.is_initialized():
+        t.cuda.current_stream().synchronize()
+
+
 def _ptr(x):
     """(address, keepalive) for a torch tensor / numpy array / None."""
     if x is None:
@@ -200,6 +210,7 @@ class Context:
         if rc != STEV_OK:
             raise StevError(rc, "stev_init failed")
         self.h = h
+        self._inflight = {}
 
     def last_error(self):
         s = self.lib.stev_last_error(self.h)
@@ -241,6 +252,7 @@ class Context:
         pY, kY = _ptr(Y)
         pI, kI = _ptr(iters)
         pS, kS = _ptr(status)
+        _after_torch()
         st = Stats()
         rc = self.lib.stev_integrate(self.h, mech.h, n, pT, pP, pY, int(ld_cell), int(ld_species),
                                      float(dt_flow), C.byref(params), pI, pS, C.byref(st))
@@ -263,6 +275,7 @@ class Context:
         pI = arr(C.c_void_p, [_ptr(x)[0] for x in iters]) if iters else None
         pS = arr(C.c_void_p, [_ptr(x)[0] for x in status]) if status else None
         keep.extend([Ts, Ps, Ys, iters, status])
+        _after_torch()
         st = Stats()
         rc = self.lib.stev_integrate_batched(self.h, nb, ph, pn, pT, pP, pY, lc, ls,
                                              float(dt_flow), C.byref(params), pI, pS,
@@ -270,21 +283,34 @@ class Context:
         self._check(rc, (STEV_OK, STEV_ECELLS) if allow_failed else (STEV_OK,))
         return rc, st.as_dict()
 
-    def submit(self, mech, T, P, Y, dt_flow, params=None, iters=None, status=None):
+    def submit(self, mech, T, P, Y, dt_flow, params=None, iters=None, status=None,
+               ld_cell=None, ld_species=None):
+        """Enqueue one solve (host or device arrays); returns its ticket.  The
+        arrays are kept alive here until poll() reports the ticket done."""
         params = params or default_params()
         n = int(T.shape[0])
+        if ld_cell is None:
+            ld_cell = int(Y.shape[1]) if len(Y.shape) == 2 else mech.n_s
+        if ld_species is None:
+            ld_species = 1
+        _after_torch()
         tk = C.c_uint64()
         rc = self.lib.stev_submit(self.h, mech.h, n, _ptr(T)[0], _ptr(P)[0], _ptr(Y)[0],
-                                  int(Y.shape[1]), 1, float(dt_flow), C.byref(params),
+                                  int(ld_cell), int(ld_species), float(dt_flow), C.byref(params),
                                   _ptr(iters)[0], _ptr(status)[0], C.byref(tk))
         self._check(rc)
+        self._inflight[tk.value] = (T, P, Y, iters, status)
         return tk.value
 
     def poll(self, ticket):
+        """(rc, stats): rc is STEV_OK / STEV_ECELLS when done, STEV_EAGAIN while pending."""
         st = Stats()
         rc = self.lib.stev_poll(self.h, C.c_uint64(ticket), C.byref(st))
         if rc not in (STEV_OK, STEV_EAGAIN, STEV_ECELLS):
+            self._inflight.pop(ticket, None)
             raise StevError(rc, self.last_error())
+        if rc != STEV_EAGAIN:
+            self._inflight.pop(ticket, None)
         return rc, st.as_dict()
 
     def train_thermo_mlp(self, mech, **cfg):
@@ -330,6 +356,7 @@ class Context:
 
     def autotune(self, mech, T, P, Y, dt_flow, params=None):
         params = params or default_params()
+        _after_torch()
         self._check(self.lib.stev_autotune(self.h, mech.h, int(T.shape[0]), _ptr(T)[0],
                                            _ptr(P)[0], _ptr(Y)[0], int(Y.shape[1]), 1,
                                            float(dt_flow), C.byref(params)))

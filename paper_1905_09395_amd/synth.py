@@ -414,3 +414,18 @@ def subsample(n, k, seed):
     if k >= n:
         return np.arange(n)
     return np.sort(rng.choice(n, size=k, replace=False))
+
+
+def make_batches(n_batches=64, lo=256, hi=131072, seed=103):
+    """Independent cell batches of log-uniform sizes; even batches are
+    6-species cells, odd batches 19-species cells.  Returns a list of
+    (mechanism key 6|19, T, P, Y)."""
+    sizes = batch_sizes(n_batches, lo, hi, seed)
+    out = []
+    for b, n in enumerate(sizes):
+        s = seed * 1000 + b
+        if b % 2 == 0:
+            out.append((6,) + make_cells_mech6(int(n), seed=s))
+        else:
+            out.append((19,) + make_cells_mech19(int(n), seed=s))
+    return out

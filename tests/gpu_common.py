@@ -8,9 +8,11 @@ oracle itself, a relative perturbation of 1e-15 of the initial state changes
 nearly depleted species by O(1) at t_f.  No implementation whose arithmetic
 differs at the last bit (exp/log, FMA contraction, summation order) can match
 such cells to 1e-9.  The oracle therefore also reports, per cell, the spread
-of its own results over an ensemble of eight perturbed runs (initial state
-moved by a few ulps of the precision under test; for FP32 also rounding
-noise injected into the net rates):
+of its own results over an ensemble of perturbed runs: T and every Y_k moved
+independently by a few ulps of the precision under test (as rounding the
+inputs to that precision moves them), and for FP32 also rounding noise
+injected into the net rates.  Eight members run for every cell; cells that
+these mark as ill-conditioned get 32 in all:
 
 * well-conditioned cells (ensemble spread < tolerance/100 on T and on every
   judged Y, equal iteration counts) must meet the stated tolerance, and in
@@ -39,7 +41,11 @@ TOL = {stev.F64: (1e-9, 1e-9, 1e-10), stev.F32: (1e-4, 1e-3, 1e-6)}
 ENS_EPS = {stev.F64: 2e-15, stev.F32: 2.4e-7}
 ENS_NOISE = {stev.F64: 0.0, stev.F32: 4e-6}
 SPREAD_FACTOR = 10.0
-ENS_MEMBERS = ((1, 0), (-1, 0), (0, 1), (0, -1), (1, 1), (-1, -1), (1, -1), (-1, 1))
+# members: T and every Y_k moved independently by eps * U[-1, 1] (as the
+# rounding of each input value to the precision under test moves them);
+# cells whose spread marks them ill-conditioned get the extra members
+ENS_MEMBERS = 8
+ENS_MEMBERS_ILL = 32
 
 
 def say(*a):
@@ -66,25 +72,49 @@ def run_gpu(ctx, m, T, P, Y, dt, precision=stev.F64, **kw):
                 rc=rc, stats=stats)
 
 
+def _spread_says_ill(o, precision):
+    tT, tY, thr = TOL[precision]
+    fin = np.isfinite(o["T"])
+    Tref = np.where(fin, o["T"], 1.0)
+    mask = (o["Y"] > thr) & fin[:, None]
+    sprT = o["spread_T"] / np.abs(Tref)
+    sprY = np.where(mask, o["spread_Y"] / np.where(mask, o["Y"], 1.0), 0.0).max(axis=1)
+    return ~((sprT < tT / 100) & (sprY < tY / 100) & (o["spread_iters"] == 0))
+
+
 def oracle_ensemble(om, T, P, Y, dt, precision=stev.F64, **kw):
     """Oracle result plus the spread of its own results over perturbed inputs."""
+    T = np.asarray(T, dtype=np.float64)
+    P = np.asarray(P, dtype=np.float64)
+    Y = np.asarray(Y, dtype=np.float64)
     base = oracle.integrate(om, T, P, Y, dt, **kw)
     eps = ENS_EPS[precision]
     noise = ENS_NOISE[precision]
-    dT = np.zeros_like(base["T"])
-    dY = np.zeros_like(base["Y"])
-    dI = np.zeros_like(base["iters"])
-    for i, (sT, sY) in enumerate(ENS_MEMBERS):
-        r = oracle.integrate(om, np.asarray(T) * (1 + sT * eps), P,
-                             np.asarray(Y) * (1 + sY * eps), dt, noise_eps=noise,
-                             noise_seed=1000 + i, **kw)
-        ok = np.isfinite(r["T"]) & np.isfinite(base["T"])
-        dT = np.maximum(dT, np.where(ok, np.abs(r["T"] - base["T"]), 0.0))
-        dY = np.maximum(dY, np.where(ok[:, None], np.abs(r["Y"] - base["Y"]), 0.0))
-        dI = np.maximum(dI, np.abs(r["iters"] - base["iters"]))
-    base["spread_T"] = dT
-    base["spread_Y"] = dY
-    base["spread_iters"] = dI
+    base["spread_T"] = np.zeros_like(base["T"])
+    base["spread_Y"] = np.zeros_like(base["Y"])
+    base["spread_iters"] = np.zeros_like(base["iters"])
+
+    def members(cells, first, last):
+        for i in range(first, last):
+            rng = np.random.default_rng(5000 + i)
+            uT = rng.uniform(-1.0, 1.0, len(T))[cells]
+            uY = rng.uniform(-1.0, 1.0, Y.shape)[cells]
+            r = oracle.integrate(om, T[cells] * (1 + eps * uT), P[cells],
+                                 Y[cells] * (1 + eps * uY), dt, noise_eps=noise,
+                                 noise_seed=1000 + i, **kw)
+            b = {k: base[k][cells] for k in ("T", "Y", "iters")}
+            ok = np.isfinite(r["T"]) & np.isfinite(b["T"])
+            base["spread_T"][cells] = np.maximum(base["spread_T"][cells],
+                                                 np.where(ok, np.abs(r["T"] - b["T"]), 0.0))
+            base["spread_Y"][cells] = np.maximum(
+                base["spread_Y"][cells], np.where(ok[:, None], np.abs(r["Y"] - b["Y"]), 0.0))
+            base["spread_iters"][cells] = np.maximum(base["spread_iters"][cells],
+                                                     np.abs(r["iters"] - b["iters"]))
+
+    members(np.arange(len(T)), 0, ENS_MEMBERS)
+    ill = np.where(_spread_says_ill(base, precision))[0]
+    if len(ill):
+        members(ill, ENS_MEMBERS, ENS_MEMBERS_ILL)
     return base
 
 

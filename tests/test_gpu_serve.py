@@ -1,0 +1,190 @@
+"""Serving: stev_submit / stev_poll with continuous batching and admission by
+HBM budget.  Each result is the same alone and in the mix (bit for bit: a
+cell's result depends on the cell only), served results agree with the FP64
+oracle, and admission, failure and ticket handling behave as documented."""
+
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1905_09395_amd import stev, synth
+from tests.gpu_common import judge, oracle_ensemble, say
+
+pytestmark = pytest.mark.gpu
+DT = 1e-4
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    assert torch.cuda.is_available(), "GPU test needs a HIP device"
+    c = stev.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def mechs(ctx):
+    out = {}
+    for key, m in ((6, synth.make_mech6()), (19, synth.make_mech19()), (53, synth.make_mech53())):
+        gm = ctx.mechanism(m)
+        rep = ctx.train_thermo_mlp(gm, epochs=20, n_samples=1 << 18, batch=4096, seed=104)
+        say(f"mech{key}: network test loss {rep['test_loss']:.2e}")
+        out[key] = (m, gm, oracle.OracleMech(m))
+    return out
+
+
+def cells(key, n, seed):
+    if key == 6:
+        return synth.make_cells_mech6(n, seed=seed)
+    return synth.make_cells_split(n, key, seed)
+
+
+def make_requests(n_req, lo, hi, seed):
+    rng = np.random.default_rng(seed)
+    sizes = np.round(np.exp(rng.uniform(np.log(lo), np.log(hi), n_req))).astype(int)
+    keys = rng.choice([6, 19, 53], n_req)
+    return [(int(k), *cells(int(k), int(n), seed * 100 + i)) for i, (k, n) in
+            enumerate(zip(keys, sizes))]
+
+
+def host_req(key, T, P, Y, dtype):
+    return dict(key=key, T=np.ascontiguousarray(T, dtype=dtype),
+                P=np.ascontiguousarray(P, dtype=dtype), Y=np.ascontiguousarray(Y, dtype=dtype),
+                it=np.zeros(len(T), np.int32), st=np.zeros(len(T), np.uint8))
+
+
+def wait(ctx, tickets, timeout=120.0):
+    out = {}
+    t0 = time.time()
+    while len(out) < len(tickets):
+        for tk in tickets:
+            if tk in out:
+                continue
+            rc, st = ctx.poll(tk)
+            if rc != stev.STEV_EAGAIN:
+                out[tk] = (rc, st)
+        assert time.time() - t0 < timeout, "requests did not finish"
+        time.sleep(2e-4)
+    return out
+
+
+def test_same_result_alone_and_in_mix(ctx, mechs):
+    """FP32 + thermo network over 6-, 19- and 53-species requests of uneven
+    sizes, host arrays: alone (one request in flight) vs all submitted at
+    once, and vs plain stev_integrate."""
+    reqs = make_requests(18, 256, 20000, seed=105)
+    prm = stev.default_params(precision=stev.F32, thermo=stev.THERMO_MLP)
+    alone = []
+    for key, T, P, Y in reqs:
+        r = host_req(key, T, P, Y, np.float32)
+        tk = ctx.submit(mechs[key][1], r["T"], r["P"], r["Y"], DT, params=prm, iters=r["it"],
+                        status=r["st"])
+        (rc, st), = wait(ctx, [tk]).values()
+        assert rc == stev.STEV_OK and st["n_cells"] == len(T) and st["latency_ms"] > 0
+        alone.append(r)
+    mix = [host_req(key, T, P, Y, np.float32) for key, T, P, Y in reqs]
+    t0 = time.time()
+    tks = [ctx.submit(mechs[r["key"]][1], r["T"], r["P"], r["Y"], DT, params=prm, iters=r["it"],
+                      status=r["st"]) for r in mix]
+    done = wait(ctx, tks)
+    lat = sorted(st["latency_ms"] for _, st in done.values())
+    say(f"mix of {len(mix)} requests, {sum(len(r['T']) for r in mix)} cells: "
+        f"{1e3 * (time.time() - t0):.1f} ms, latency p50 {lat[len(lat) // 2]:.1f} ms "
+        f"max {lat[-1]:.1f} ms")
+    assert all(rc == stev.STEV_OK for rc, _ in done.values())
+    for i, (a, m) in enumerate(zip(alone, mix)):
+        assert np.array_equal(a["T"], m["T"]) and np.array_equal(a["Y"], m["Y"]), f"request {i}"
+        assert np.array_equal(a["it"], m["it"])
+    # and the same as the plain entry point
+    for i, (key, T, P, Y) in enumerate(reqs[:6]):
+        r = host_req(key, T, P, Y, np.float32)
+        ctx.integrate(mechs[key][1], r["T"], r["P"], r["Y"], DT, params=prm, iters=r["it"])
+        assert np.array_equal(r["T"], mix[i]["T"]) and np.array_equal(r["Y"], mix[i]["Y"])
+
+
+def test_served_results_match_oracle(ctx, mechs):
+    """Served FP64 and FP32 (polynomial thermo) results against the oracle."""
+    import torch
+    reqs = make_requests(9, 64, 600, seed=106)
+    for prec, dt in ((stev.F64, np.float64), (stev.F32, np.float32)):
+        prm = stev.default_params(precision=prec)
+        tdt = torch.float64 if prec == stev.F64 else torch.float32
+        # device arrays, solved in place
+        dev = [dict(key=k, T=torch.tensor(T, dtype=tdt, device="cuda"),
+                    P=torch.tensor(P, dtype=tdt, device="cuda"),
+                    Y=torch.tensor(Y, dtype=tdt, device="cuda"),
+                    it=torch.zeros(len(T), dtype=torch.int32, device="cuda"),
+                    st=torch.zeros(len(T), dtype=torch.uint8, device="cuda"))
+               for k, T, P, Y in reqs]
+        tks = [ctx.submit(mechs[d["key"]][1], d["T"], d["P"], d["Y"], DT, params=prm,
+                          iters=d["it"], status=d["st"]) for d in dev]
+        wait(ctx, tks)
+        for key in (6, 19, 53):
+            sel = [i for i, r in enumerate(reqs) if r[0] == key]
+            if not sel:
+                continue
+            T = np.concatenate([reqs[i][1] for i in sel])
+            P = np.concatenate([reqs[i][2] for i in sel])
+            Y = np.concatenate([reqs[i][3] for i in sel])
+            g = dict(T=np.concatenate([dev[i]["T"].cpu().double().numpy() for i in sel]),
+                     Y=np.concatenate([dev[i]["Y"].cpu().double().numpy() for i in sel]),
+                     iters=np.concatenate([dev[i]["it"].cpu().numpy() for i in sel]).astype(np.int64),
+                     status=np.concatenate([dev[i]["st"].cpu().numpy() for i in sel]))
+            k = synth.subsample(len(T), 160, seed=key)
+            g = {n: v[k] for n, v in g.items()}
+            o = oracle_ensemble(mechs[key][2], T[k], P[k], Y[k], DT, prec)
+            judge(g, o, prec, f"served mech{key} prec={prec}")
+
+
+def test_admission_by_hbm_budget(mechs):
+    """A budget that holds only a few requests' staging at a time: everything
+    still completes, correctly; a request that can never fit is refused."""
+    import torch
+    small = stev.Context(0, hbm_budget=40 << 20)
+    try:
+        m19 = small.mechanism(mechs[19][0])
+        reqs = [(19, *cells(19, 60000, 900 + i)) for i in range(8)]   # ~5.3 MB staging each
+        prm = stev.default_params(precision=stev.F32)
+        rs = [host_req(*r, np.float32) for r in reqs]
+        tks = [small.submit(m19, r["T"], r["P"], r["Y"], DT, params=prm, iters=r["it"])
+               for r in rs]
+        done = wait(small, tks)
+        assert all(rc == stev.STEV_OK for rc, _ in done.values())
+        for (key, T, P, Y), r in zip(reqs[:2], rs[:2]):
+            ref = host_req(key, T, P, Y, np.float32)
+            small.integrate(m19, ref["T"], ref["P"], ref["Y"], DT, params=prm)
+            assert np.array_equal(ref["T"], r["T"]) and np.array_equal(ref["Y"], r["Y"])
+        big = host_req(19, *cells(19, 600000, 3), np.float32)     # ~53 MB staging
+        with pytest.raises(stev.StevError) as e:
+            small.submit(m19, big["T"], big["P"], big["Y"], DT, params=prm)
+        assert e.value.code == stev.STEV_ENOMEM
+        m19.close()
+    finally:
+        small.close()
+    torch.cuda.synchronize()
+
+
+def test_failed_cells_and_tickets(ctx, mechs):
+    prm = stev.default_params(precision=stev.F64)
+    good = host_req(6, *cells(6, 300, 1), np.float64)
+    bad = host_req(6, *cells(6, 300, 2), np.float64)
+    bad["T"][17] = np.nan
+    tg = ctx.submit(mechs[6][1], good["T"], good["P"], good["Y"], DT, params=prm, status=good["st"])
+    tb = ctx.submit(mechs[6][1], bad["T"], bad["P"], bad["Y"], DT, params=prm, status=bad["st"])
+    res = wait(ctx, [tg, tb])
+    assert res[tg][0] == stev.STEV_OK and res[tb][0] == stev.STEV_ECELLS
+    assert res[tb][1]["n_failed"] == 1 and bad["st"][17] == 1
+    assert np.count_nonzero(bad["st"]) == 1 and np.count_nonzero(good["st"]) == 0
+    # a ticket is released once its result has been reported
+    with pytest.raises(stev.StevError) as e:
+        ctx.poll(tg)
+    assert e.value.code == stev.STEV_ENOTFOUND
+    with pytest.raises(stev.StevError) as e:
+        ctx.poll(123456789)
+    assert e.value.code == stev.STEV_ENOTFOUND
+    with pytest.raises(stev.StevError) as e:
+        ctx.submit(mechs[6][1], good["T"][:0], good["P"][:0], good["Y"][:0], DT)
+    assert e.value.code == stev.STEV_EINVAL

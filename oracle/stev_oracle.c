@@ -171,13 +171,39 @@ double orc_step_size(const orc_params *p, int n_s, const double *Y,
 }
 
 /* Section 2.3, Eq 9: plain DFT magnitudes, X_k = sum_m x_m e^{-2 pi i k m / W}. */
+/* cos and sin of 2 pi k m / W, evaluated once per window length (the same
+ * calls, hence the same values, as evaluating them inside the sums). */
+#define ORC_TAB_MAX 64
+static double orc_tab_cos[ORC_TAB_MAX][ORC_TAB_MAX], orc_tab_sin[ORC_TAB_MAX][ORC_TAB_MAX];
+static int orc_tab_W = 0;
+
+static void orc_dft_table(int W) {
+  if (W == orc_tab_W || W > ORC_TAB_MAX) return;
+  for (int k = 0; k < W; ++k)
+    for (int mm = 0; mm < W; ++mm) {
+      double ang = 2.0 * ORC_PI * (double)k * (double)mm / (double)W;
+      orc_tab_cos[k][mm] = cos(ang);
+      orc_tab_sin[k][mm] = sin(ang);
+    }
+  orc_tab_W = W;
+}
+
 void orc_dft_mag(const double *x, int W, double *D) {
+  const int tab = (W == orc_tab_W);
   for (int k = 0; k < W; ++k) {
     double re = 0.0, im = 0.0;
     for (int mm = 0; mm < W; ++mm) {
-      double ang = 2.0 * ORC_PI * (double)k * (double)mm / (double)W;
-      re += x[mm] * cos(ang);
-      im -= x[mm] * sin(ang);
+      double c, sn;
+      if (tab) {
+        c = orc_tab_cos[k][mm];
+        sn = orc_tab_sin[k][mm];
+      } else {
+        double ang = 2.0 * ORC_PI * (double)k * (double)mm / (double)W;
+        c = cos(ang);
+        sn = sin(ang);
+      }
+      re += x[mm] * c;
+      im -= x[mm] * sn;
     }
     D[k] = sqrt(re * re + im * im);
   }
@@ -296,6 +322,7 @@ int orc_integrate(const orc_mech *m, const orc_params *p, long long n,
                   double tf, long long *iters, unsigned char *status,
                   double *margin_dft, double *margin_y, int nthreads) {
   int worst = 0;
+  if (p->dft_window > 0) orc_dft_table(p->dft_window);   /* before the threads start */
 #ifdef _OPENMP
   if (nthreads <= 0) nthreads = omp_get_max_threads();
 #pragma omp parallel for schedule(dynamic, 4) num_threads(nthreads) reduction(max : worst)

@@ -111,9 +111,12 @@ def oracle_ensemble(om, T, P, Y, dt, precision=stev.F64, **kw):
             base["spread_iters"][cells] = np.maximum(base["spread_iters"][cells],
                                                      np.abs(r["iters"] - b["iters"]))
 
+    say(f"  oracle ensemble: {len(T)} cells x {ENS_MEMBERS} members")
     members(np.arange(len(T)), 0, ENS_MEMBERS)
     ill = np.where(_spread_says_ill(base, precision))[0]
     if len(ill):
+        say(f"  oracle ensemble: {len(ill)} ill-conditioned cells x "
+            f"{ENS_MEMBERS_ILL - ENS_MEMBERS} more members")
         members(ill, ENS_MEMBERS, ENS_MEMBERS_ILL)
     return base
 

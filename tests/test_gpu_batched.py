@@ -171,8 +171,10 @@ def test_destroyed_mechanism_drops_recorded_sequences(ctx):
         Pt = torch.tensor(P, dtype=torch.float64, device="cuda")
         Yt = torch.tensor(Y, dtype=torch.float64, device="cuda")
         it = torch.zeros(500, dtype=torch.int32, device="cuda")
-        ctx.integrate_batched([gm], [Tt], [Pt], [Yt], DT, iters=[it])
-        g = dict(T=Tt.cpu().numpy(), Y=Yt.cpu().numpy(), iters=it.cpu().numpy().astype(np.int64))
+        stt = torch.zeros(500, dtype=torch.uint8, device="cuda")
+        ctx.integrate_batched([gm], [Tt], [Pt], [Yt], DT, iters=[it], status=[stt])
+        g = dict(T=Tt.cpu().numpy(), Y=Yt.cpu().numpy(), iters=it.cpu().numpy().astype(np.int64),
+                 status=stt.cpu().numpy())
         if first is None:
             first = g
             judge(g, o, stev.F64, "batched, fresh mechanism")

@@ -133,7 +133,7 @@ def test_served_results_match_oracle(ctx, mechs):
                      Y=np.concatenate([dev[i]["Y"].cpu().double().numpy() for i in sel]),
                      iters=np.concatenate([dev[i]["it"].cpu().numpy() for i in sel]).astype(np.int64),
                      status=np.concatenate([dev[i]["st"].cpu().numpy() for i in sel]))
-            k = synth.subsample(len(T), 160, seed=key)
+            k = synth.subsample(len(T), 64 if key == 53 else 160, seed=key)
             g = {n: v[k] for n, v in g.items()}
             o = oracle_ensemble(mechs[key][2], T[k], P[k], Y[k], DT, prec)
             judge(g, o, prec, f"served mech{key} prec={prec}")
@@ -153,6 +153,9 @@ def test_admission_by_hbm_budget(mechs):
                for r in rs]
         done = wait(small, tks)
         assert all(rc == stev.STEV_OK for rc, _ in done.values())
+        waited = sum(st["budget_waits"] > 0 for _, st in done.values())
+        say(f"admission: {waited} of {len(tks)} requests waited for HBM budget")
+        assert waited > 0
         for (key, T, P, Y), r in zip(reqs[:2], rs[:2]):
             ref = host_req(key, T, P, Y, np.float32)
             small.integrate(m19, ref["T"], ref["P"], ref["Y"], DT, params=prm)

@@ -65,7 +65,7 @@ def measured_traffic(precision, cells):
 def traffic_probe(precision):
     """One plain copy of known size (counter calibration), then one step."""
     import torch
-    n = 64 * 1024 * 1024
+    n = PROBE_COPY_BYTES // 4
     x = torch.ones(n, device="cuda")
     y = torch.empty_like(x)
     torch.cuda.synchronize()
@@ -100,6 +100,73 @@ def cpu_baseline(mech, T, P, Y, dt, budget_s=12.0):
             "sample": f"{total_cells} cells drawn (seeded, without replacement) from the same "
                       f"262144-cell field in batches of doubling size, {total_s:.1f} s of "
                       f"FP64 oracle time with OpenMP over {cores} host threads"}
+
+
+PROBE_COPY_BYTES = 64 * 1024 * 1024 * 4
+
+
+def traffic_summary(fetch_csv, write_csv, precision, cells):
+    """Turn two rocprofv3 --pmc runs of `bench.py --probe` (FETCH_SIZE, then
+    WRITE_SIZE; KiB per dispatch) into HBM bytes per integration launch,
+    each counter scaled by what it reads for the probe's plain copy of known
+    size.  Writes profiles/stev_traffic_<prec>_mech19_<cells>.json and .md."""
+    import csv
+
+    def read(path, counter):
+        copy, stev = [], []
+        with open(path) as f:
+            for row in csv.DictReader(f):
+                if row["Counter_Name"] != counter:
+                    continue
+                v = float(row["Counter_Value"])
+                if "copyBuffer" in row["Kernel_Name"]:
+                    copy.append(v)
+                elif "stev_persistent" in row["Kernel_Name"]:
+                    stev.append(v)
+        assert copy and len(stev) == 1, f"{path}: expected copies and one integration launch"
+        return max(copy), stev[0]
+
+    fc, fs = read(fetch_csv, "FETCH_SIZE")
+    wc, ws = read(write_csv, "WRITE_SIZE")
+    kib = PROBE_COPY_BYTES / 1024.0
+    f_fac, w_fac = kib / fc, kib / wc
+    fetch_b = fs * f_fac * 1024.0
+    write_b = ws * w_fac * 1024.0
+    rsz = 8 if precision == "f64" else 4
+    algo = cells * (2 * 19 + 3) * rsz
+    rec = {"kernel": "stev_persistent", "precision": precision, "cells": cells,
+           "fetch_kib_raw": fs, "write_kib_raw": ws,
+           "copy_fetch_kib_raw": fc, "copy_write_kib_raw": wc,
+           "fetch_scale": f_fac, "write_scale": w_fac,
+           "fetch_bytes": fetch_b, "write_bytes": write_b,
+           "traffic_bytes_per_launch": fetch_b + write_b,
+           "algorithmic_bytes_per_launch": algo,
+           "kernel_sources_sha256": kernel_sources_sha(),
+           "commands": [
+               "rocprofv3 --pmc FETCH_SIZE -d gpurun_out/pmc_fetch -o t --output-format csv "
+               f"-- python bench.py --probe --precision {precision}",
+               "rocprofv3 --pmc WRITE_SIZE -d gpurun_out/pmc_write -o t --output-format csv "
+               f"-- python bench.py --probe --precision {precision}",
+               "python bench.py --traffic-summary gpurun_out/pmc_fetch/t_counter_collection.csv "
+               f"gpurun_out/pmc_write/t_counter_collection.csv --precision {precision}"]}
+    base = os.path.join(ROOT, "profiles", f"stev_traffic_{precision}_mech19_{cells}")
+    with open(base + ".json", "w") as f:
+        json.dump(rec, f, indent=1)
+    with open(base + ".md", "w") as f:
+        f.write(f"# HBM traffic of one stev_persistent launch ({precision}, 19 species, "
+                f"{cells} cells)\n\n")
+        f.write("Commands (committed files only):\n\n")
+        for c in rec["commands"]:
+            f.write(f"    {c}\n")
+        f.write(f"\n| quantity | value |\n|---|---|\n")
+        f.write(f"| FETCH_SIZE, launch (KiB, raw) | {fs:.0f} |\n")
+        f.write(f"| WRITE_SIZE, launch (KiB, raw) | {ws:.0f} |\n")
+        f.write(f"| copy of {PROBE_COPY_BYTES} B: FETCH_SIZE / WRITE_SIZE (KiB, raw) | "
+                f"{fc:.0f} / {wc:.0f} |\n")
+        f.write(f"| scale FETCH / WRITE | {f_fac:.3f} / {w_fac:.3f} |\n")
+        f.write(f"| read + written per launch (MB) | {fetch_b / 1e6:.1f} + {write_b / 1e6:.1f} |\n")
+        f.write(f"| algorithmic state bytes (MB) | {algo / 1e6:.1f} |\n")
+    print(json.dumps(rec))
 
 
 def base_record(args, value, el, dtype, workload, **config):
@@ -287,7 +354,7 @@ def run_serve(args):
     from paper_1905_09395_amd import stev, synth
     dt = 1e-4
     rng = np.random.default_rng(105)
-    n_req = 40
+    n_req = 32
     sizes = np.round(np.exp(rng.uniform(np.log(1024), np.log(524288), n_req))).astype(int)
     keys = rng.choice([6, 19, 53], n_req)
     mean_cells = 83879.0
@@ -319,6 +386,8 @@ def run_serve(args):
     for r in reqs:
         ctx.integrate(mechs[r["k"]], r["T"], r["P"], r["Y"], dt, params=prm)
     cap = total / (time.perf_counter() - t0)
+    print(f"serve: {n_req} requests, {total} cells; plain capacity {cap:.0f} cells/s",
+          file=sys.stderr, flush=True)
 
     def arrivals(load):
         lam = load * cap / mean_cells
@@ -382,6 +451,7 @@ def run_serve(args):
             l, m, w = serve_run(at)
             ls.append(l); ms.append(m); bw.append(w)
         lp, mp = plain_run(at)
+        print(f"serve: load {load} done", file=sys.stderr, flush=True)
         L = np.concatenate(ls)
         rows[str(load)] = dict(
             serve_p50_ms=1e3 * float(np.quantile(L, .5)), serve_p99_ms=1e3 * float(np.quantile(L, .99)),
@@ -391,7 +461,7 @@ def run_serve(args):
             plain_cells_per_s=total / mp)
     top = rows["0.95"]
     out = base_record(args, top["serve_cells_per_s"], float(np.sum(ms)), "f32",
-                      "serving: Poisson arrivals, 40 requests of log-uniform size in "
+                      "serving: Poisson arrivals, 32 requests of log-uniform size in "
                       "[1024, 524288] cells over 6-, 19- and 53-species mechanisms, FP32 + "
                       "thermo network, host-resident pinned requests admitted by a 512 MiB HBM "
                       "budget; value at load 0.95",
@@ -413,7 +483,12 @@ def main():
     ap.add_argument("--probe", action="store_true",
                     help="counter-calibration run: one plain copy, then one step")
     ap.add_argument("--workload", default="plain", choices=["plain", "batched", "mlp", "serve"])
+    ap.add_argument("--traffic-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="CPU only: write the HBM traffic summary from two counter runs")
     args = ap.parse_args()
+    if args.traffic_summary:
+        traffic_summary(*args.traffic_summary, args.precision, args.cells)
+        return
     if args.probe:
         args.steps, args.warmup, args.no_cpu = 1, 0, True
     if args.gpus != 1:

@@ -46,17 +46,22 @@ constexpr int kRxStride = 32;
 // the mechanism read valid, harmless data instead of branching around it:
 // the dummy species has zero coefficients and no reactions; the dummy
 // reaction has ln A = -inf (k_f = 0) and all slots on the unit entry.
+// Species -> reaction lists of up to this many entries are walked from
+// registers with a fixed trip count (rows padded with the zero-rate entry).
+constexpr int kCsrReg = 24;
+
 struct MechLayout {
   int n_s, n_r, n_rev, nnz_csr;
   int has_frac;        // a slot carries an order other than 1 (pow needed)
   int mixed_tmid;      // some reaction's participants differ in T_mid
-  int dmax;            // padded species -> reaction CSR width
+  int dmax;            // longest species -> reaction list
+  int dstride;         // CSR row stride: kCsrReg when dmax <= kCsrReg (rows padded)
   int bytes;           // total blob size (multiple of 16)
   int off_sp;          // R   [n_s+1][kSpStride]
   int off_rx;          // R   [n_r+1][kRxStride]
   int off_rxi;         // i32 [n_r+1][kMaxPart] slot species: n_s = unit entry
-  int off_cj;          // i32 [n_s+1][dmax]     reaction (packed order); n_r = zero entry
-  int off_cnu;         // R   [n_s+1][dmax]     nu (0 on padding)
+  int off_cj;          // i32 [n_s+1][dstride]  reaction (packed order); n_r = zero entry
+  int off_cnu;         // R   [n_s+1][dstride]  nu (0 on padding)
 };
 
 // Thermo network attached to a mechanism (Sec 3): 1 -> 32 -> 32 -> 2 n_s.

@@ -59,7 +59,8 @@ __device__ __forceinline__ void wave_lds_sync() {
 // group (the combining operations used here are commutative).
 template <int CTRL>
 __device__ __forceinline__ int dpp_i(int v) {
-  return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xf, 0xf, false);
+  // every control used is a full permutation of each row: all lanes written
+  return __builtin_amdgcn_mov_dpp(v, CTRL, 0xf, 0xf, false);
 }
 __device__ __forceinline__ int swap16_i(int v) {   // partner lane ^ 16
   auto p = __builtin_amdgcn_permlane16_swap((unsigned)v, (unsigned)v, false, false);
@@ -217,7 +218,9 @@ stev_persistent(const KArgs a) {
   const int *cj = reinterpret_cast<const int *>(smem + a.L.off_cj);
   const R *cnu = reinterpret_cast<const R *>(smem + a.L.off_cnu);
 
+  static_assert(CSRR == 0 || CSRR == kCsrReg, "register CSR walks padded rows of kCsrReg");
   const int n_s = a.L.n_s, n_r = a.L.n_r, n_rev = a.L.n_rev, dmax = a.L.dmax;
+  const int dstride = a.L.dstride;
   const int has_frac = a.L.has_frac, mixed = a.L.mixed_tmid;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
@@ -277,8 +280,9 @@ stev_persistent(const KArgs a) {
 #pragma unroll
     for (int e = 0; e < (CSRR + 1) / 2; ++e) {
       const int e0 = 2 * e, e1 = 2 * e + 1;
-      const unsigned o0 = (e0 < dmax) ? (unsigned)(cj[kk[s] * dmax + e0] * CPW + gi) : (unsigned)(n_r * CPW + gi);
-      const unsigned o1 = (e1 < dmax) ? (unsigned)(cj[kk[s] * dmax + e1] * CPW + gi) : (unsigned)(n_r * CPW + gi);
+      // rows are padded to kCsrReg with the zero-rate entry n_r
+      const unsigned o0 = (unsigned)(cj[kk[s] * dstride + e0] * CPW + gi);
+      const unsigned o1 = (unsigned)(cj[kk[s] * dstride + e1] * CPW + gi);
       coff[s][e] = csr_reg ? (o0 | (o1 << 16)) : 0u;
     }
 
@@ -315,6 +319,7 @@ stev_persistent(const KArgs a) {
   long long n_fail = 0;
 
   int rs = 0;    // this cell's ring slot: sample i goes to slot i mod 13
+  bool dft_due = false;   // the ring was filled by the step just taken
   const int K = a.compact_every > 0 ? a.compact_every : 1;
   int kc = 0;    // iterations until the next refill attempt
 
@@ -374,6 +379,7 @@ stev_persistent(const KArgs a) {
             t = 0.0;
             it = 0;
             rs = 0;
+            dft_due = false;
             st = 0;
             active = true;
           } else {
@@ -391,6 +397,60 @@ stev_persistent(const KArgs a) {
     // ---- one STEV iteration ---------------------------------------------------
     const R lnT = Math<R>::lg(T);
     const R invT = R(1) / T;
+    const R lnPRT = ln_patm_r - lnT;
+    const R omlnT = R(1) - lnT;
+
+    // |DFT| of the ring filled by the previous step and the rOF update (Eqs
+    // 9-13).  Taking it here rather than at the end of that step changes
+    // nothing (the ring and rOF are untouched in between) and lets its
+    // arithmetic overlap the transcendentals below.
+    if (a.dft_on) {
+#pragma unroll
+      for (int r = 0; r < RRPL; ++r) {
+        R sp[6], dm[6];
+        R S = ring[r][0];
+#pragma unroll
+        for (int mm = 1; mm <= 6; ++mm) {
+          sp[mm - 1] = ring[r][mm] + ring[r][kWin - mm];
+          dm[mm - 1] = ring[r][mm] - ring[r][kWin - mm];
+          S += sp[mm - 1];
+        }
+        R M2 = R(0);
+#pragma unroll
+        for (int k = 4; k <= 6; ++k) {
+          R re = ring[r][0], im = R(0);
+#pragma unroll
+          for (int mm = 0; mm < 6; ++mm) {
+            re += sp[mm] * R(tw_re(k, mm + 1));
+            im += dm[mm] * R(tw_im(k, mm + 1));
+          }
+          M2 = fmax(M2, re * re + im * im);
+        }
+        const bool ring_eq = (S * S < tol_ring2 * M2) && (fabs(S) < tol_freq);  // Eqs 10, 12
+        const R upd = fmax(fmin(rOF[r] * (ring_eq ? r_fac_inv : r_fac), R(1)), rof_min);  // Eq 13
+        rOF[r] = (dft_due && jrev[r]) ? upd : rOF[r];
+      }
+    }
+
+    // rate constants (Eqs 28-30) depend on T alone: evaluate them ahead of
+    // the concentration exchange (for few reactions per lane)
+    constexpr bool kEarly = RPL <= 2;
+    R kf_e[kEarly ? RPL : 1], ek_e[kEarly ? RPL : 1];
+    if constexpr (kEarly) {
+#pragma unroll
+      for (int r = 0; r < RPL; ++r) {
+        const R *rr = rxR + jj[r] * kRxStride;
+        const R lnkf = rr[RX_LNA] + rr[RX_B] * lnT - rr[RX_TH] * invT;
+        kf_e[r] = Math<R>::ex(lnkf);
+        ek_e[r] = R(0);
+        if (n_rev > 0 && !mixed) {
+          const R *d = rr + ((T < rr[RX_TMID]) ? RX_DLO : RX_DHI);
+          const R dG = d[0] * omlnT + T * (d[1] + T * (d[2] + T * (d[3] + T * d[4]))) + d[5] * invT - d[6];
+          const R lnKc = rr[RX_DN] * lnPRT - dG;
+          ek_e[r] = Math<R>::ex(-lnKc);
+        }
+      }
+    }
 
     // thermo (Eqs 15-16) and mixture sums; with the network, cp and h come from
     // its outputs for cells inside the trained range (Sec 3)
@@ -451,8 +511,6 @@ stev_persistent(const KArgs a) {
 
     // rates (Eqs 28-30), damping (Eq 14)
     R q[RPL];
-    const R lnPRT = ln_patm_r - lnT;
-    const R omlnT = R(1) - lnT;
 #pragma unroll
     for (int r = 0; r < RPL; ++r) {
       const R *rr = rxR + jj[r] * kRxStride;
@@ -466,23 +524,34 @@ stev_persistent(const KArgs a) {
           if (o != R(1)) C[p] = (C[p] > R(0)) ? Math<R>::ex(o * Math<R>::lg(C[p])) : R(0);
         }
       }
-      const R lnkf = rr[RX_LNA] + rr[RX_B] * lnT - rr[RX_TH] * invT;
-      const R kf = Math<R>::ex(lnkf);
+      R kf;
+      if constexpr (kEarly) {
+        kf = kf_e[r < RPL ? r : 0];
+      } else {
+        const R lnkf = rr[RX_LNA] + rr[RX_B] * lnT - rr[RX_TH] * invT;
+        kf = Math<R>::ex(lnkf);
+      }
       const R pf = C[0] * C[1] * C[2];
       R qq = kf * pf;
       if (n_rev > 0) {
-        R dG;
-        if (!mixed) {
-          const R *d = rr + ((T < rr[RX_TMID]) ? RX_DLO : RX_DHI);
-          dG = d[0] * omlnT + T * (d[1] + T * (d[2] + T * (d[3] + T * d[4]))) + d[5] * invT - d[6];
+        R ek;   // 1 / K_c
+        if (kEarly && !mixed) {
+          ek = ek_e[r < RPL ? r : 0];
         } else {
-          dG = R(0);
+          R dG;
+          if (!mixed) {
+            const R *d = rr + ((T < rr[RX_TMID]) ? RX_DLO : RX_DHI);
+            dG = d[0] * omlnT + T * (d[1] + T * (d[2] + T * (d[3] + T * d[4]))) + d[5] * invT - d[6];
+          } else {
+            dG = R(0);
 #pragma unroll
-          for (int p = 0; p < kMaxPart; ++p) dG += rr[RX_NU + p] * sGb[soff[r][p]];
+            for (int p = 0; p < kMaxPart; ++p) dG += rr[RX_NU + p] * sGb[soff[r][p]];
+          }
+          const R lnKc = rr[RX_DN] * lnPRT - dG;
+          ek = Math<R>::ex(-lnKc);
         }
-        const R lnKc = rr[RX_DN] * lnPRT - dG;
         const R pr = C[3] * C[4] * C[5];
-        const R qrev = kf * (pf - pr * Math<R>::ex(-lnKc));
+        const R qrev = kf * (pf - pr * ek);
         qq = jrev[r] ? qrev : qq;
       }
       q[r] = qq;
@@ -498,16 +567,18 @@ stev_persistent(const KArgs a) {
     R tst = R(INFINITY);
 #pragma unroll
     for (int s = 0; s < SPL; ++s) {
-      const R *nu = cnu + kk[s] * dmax;
+      const R *nu = cnu + kk[s] * dstride;
       R om = R(0);
       if (csr_reg) {
+        // fixed trip count, no branches: all loads issue back to back; the
+        // padding adds nu = 0 times the zero entry, which leaves om unchanged
 #pragma unroll
-        for (int e = 0; e < (CSRR + 1) / 2; ++e) {
-          if (2 * e < dmax) om += nu[2 * e] * sQ[coff[s][e] & 0xffffu];
-          if (2 * e + 1 < dmax) om += nu[2 * e + 1] * sQ[coff[s][e] >> 16];
+        for (int e = 0; e < CSRR; ++e) {
+          const unsigned o = (e & 1) ? (coff[s][e >> 1] >> 16) : (coff[s][e >> 1] & 0xffffu);
+          om += nu[e] * sQ[o];
         }
       } else {
-        const int *jr = cj + kk[s] * dmax;
+        const int *jr = cj + kk[s] * dstride;
         for (int e = 0; e < dmax; ++e) om += nu[e] * sQ[jr[e] * CPW + gi];
       }
       const R rk = Wk[s] * om * inv_rho;
@@ -573,32 +644,7 @@ stev_persistent(const KArgs a) {
         }
       }
       rs = commit ? (rs == kWin - 1 ? 0 : rs + 1) : rs;
-      const bool full = commit && it >= kWin;
-#pragma unroll
-      for (int r = 0; r < RRPL; ++r) {
-        R sp[6], dm[6];
-        R S = ring[r][0];
-#pragma unroll
-        for (int mm = 1; mm <= 6; ++mm) {
-          sp[mm - 1] = ring[r][mm] + ring[r][kWin - mm];
-          dm[mm - 1] = ring[r][mm] - ring[r][kWin - mm];
-          S += sp[mm - 1];
-        }
-        R M2 = R(0);
-#pragma unroll
-        for (int k = 4; k <= 6; ++k) {
-          R re = ring[r][0], im = R(0);
-#pragma unroll
-          for (int mm = 0; mm < 6; ++mm) {
-            re += sp[mm] * R(tw_re(k, mm + 1));
-            im += dm[mm] * R(tw_im(k, mm + 1));
-          }
-          M2 = fmax(M2, re * re + im * im);
-        }
-        const bool ring_eq = (S * S < tol_ring2 * M2) && (fabs(S) < tol_freq);  // Eqs 10, 12
-        const R upd = fmax(fmin(rOF[r] * (ring_eq ? r_fac_inv : r_fac), R(1)), rof_min);  // Eq 13
-        rOF[r] = (full && jrev[r]) ? upd : rOF[r];
-      }
+      dft_due = commit && it >= kWin;   // the ring is full: Eqs 9-13 at the next pass
     }
   }
 

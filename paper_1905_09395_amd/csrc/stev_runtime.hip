@@ -224,7 +224,8 @@ static void pack_blob(const stev_mech *m, std::vector<unsigned char> &blob, Mech
   L.has_frac = m->has_frac;
   L.mixed_tmid = m->mixed_tmid;
   L.dmax = m->dmax;
-  L.nnz_csr = (n_s + 1) * m->dmax;
+  L.dstride = m->dmax <= kCsrReg ? kCsrReg : m->dmax;
+  L.nnz_csr = (n_s + 1) * L.dstride;
   int off = 0;
   L.off_sp = off;   off = align16(off + (n_s + 1) * kSpStride * (int)sizeof(R));
   L.off_rx = off;   off = align16(off + (n_r + 1) * kRxStride * (int)sizeof(R));
@@ -291,10 +292,10 @@ static void pack_blob(const stev_mech *m, std::vector<unsigned char> &blob, Mech
   R *cnu = reinterpret_cast<R *>(blob.data() + L.off_cnu);
   for (int k = 0; k <= n_s; ++k) {
     const int deg = k < n_s ? m->csr_ptr[k + 1] - m->csr_ptr[k] : 0;
-    for (int e = 0; e < m->dmax; ++e) {
+    for (int e = 0; e < L.dstride; ++e) {
       const bool used = e < deg;
-      cj[k * m->dmax + e] = used ? m->csr_j[m->csr_ptr[k] + e] : n_r;
-      cnu[k * m->dmax + e] = used ? (R)m->csr_nu[m->csr_ptr[k] + e] : (R)0;
+      cj[k * L.dstride + e] = used ? m->csr_j[m->csr_ptr[k] + e] : n_r;
+      cnu[k * L.dstride + e] = used ? (R)m->csr_nu[m->csr_ptr[k] + e] : (R)0;
     }
   }
 }

@@ -29,7 +29,7 @@ def m19(ctx):
     m = synth.make_mech19()
     gm = ctx.mechanism(m)
     say("training the 19-species thermo network (2^20 samples)")
-    rep = ctx.train_thermo_mlp(gm, epochs=100, n_samples=1 << 20, batch=4096, lr=3e-3, seed=104)
+    rep = ctx.train_thermo_mlp(gm, epochs=300, n_samples=1 << 20, batch=8192, lr=3e-3, seed=104)
     say(f"train report {rep}")
     return m, gm, oracle.OracleMech(m), rep
 

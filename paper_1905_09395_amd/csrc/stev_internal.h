@@ -49,13 +49,18 @@ constexpr int kRxStride = 32;
 // Species -> reaction lists of up to this many entries are walked from
 // registers with a fixed trip count (rows padded with the zero-rate entry).
 constexpr int kCsrReg = 24;
+// Longer lists are walked in chunks of this many entries (rows padded to a
+// multiple of it), so a chunk's loads are all in flight at once.
+constexpr int kCsrChunk = 8;
+static_assert(kCsrReg % kCsrChunk == 0, "register rows must also pad to whole chunks");
 
 struct MechLayout {
   int n_s, n_r, n_rev, nnz_csr;
   int has_frac;        // a slot carries an order other than 1 (pow needed)
   int mixed_tmid;      // some reaction's participants differ in T_mid
   int dmax;            // longest species -> reaction list
-  int dstride;         // CSR row stride: kCsrReg when dmax <= kCsrReg (rows padded)
+  int dstride;         // CSR row stride: kCsrReg when dmax <= kCsrReg, else dmax
+                       // rounded up to kCsrChunk (rows padded with the zero entry)
   int bytes;           // total blob size (multiple of 16)
   int off_sp;          // R   [n_s+1][kSpStride]
   int off_rx;          // R   [n_r+1][kRxStride]

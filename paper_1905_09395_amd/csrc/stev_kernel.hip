@@ -511,6 +511,38 @@ stev_persistent(const KArgs a) {
 
     // rates (Eqs 28-30), damping (Eq 14)
     R q[RPL];
+    if (!has_frac && !mixed) {
+      // integer orders and per-reaction Gibbs sums: one straight-line block
+      // over the lane's reactions, so their loads and exponentials interleave
+#pragma unroll
+      for (int r = 0; r < RPL; ++r) {
+        const R *rr = rxR + jj[r] * kRxStride;
+        R C[kMaxPart];
+#pragma unroll
+        for (int p = 0; p < kMaxPart; ++p) C[p] = sC[soff[r][p]];
+        R kf, ek;   // k_f and 1 / K_c
+        if constexpr (kEarly) {
+          kf = kf_e[r < RPL ? r : 0];
+          ek = ek_e[r < RPL ? r : 0];
+        } else {
+          const R lnkf = rr[RX_LNA] + rr[RX_B] * lnT - rr[RX_TH] * invT;
+          kf = Math<R>::ex(lnkf);
+          const R *d = rr + ((T < rr[RX_TMID]) ? RX_DLO : RX_DHI);
+          const R dG = d[0] * omlnT + T * (d[1] + T * (d[2] + T * (d[3] + T * d[4]))) + d[5] * invT - d[6];
+          const R lnKc = rr[RX_DN] * lnPRT - dG;
+          ek = Math<R>::ex(-lnKc);
+        }
+        const R pf = C[0] * C[1] * C[2];
+        const R pr = C[3] * C[4] * C[5];
+        const R qf = kf * pf;
+        const R qrev = kf * (pf - pr * ek);
+        const R qq = jrev[r] ? qrev : qf;
+        q[r] = qq;
+        R qe = qq;
+        if (r < RRPL) qe = jrev[r] ? rOF[r < RRPL ? r : 0] * qq : qq;
+        sQ[qrow[r]] = qe;
+      }
+    } else {
 #pragma unroll
     for (int r = 0; r < RPL; ++r) {
       const R *rr = rxR + jj[r] * kRxStride;
@@ -559,6 +591,7 @@ stev_persistent(const KArgs a) {
       if (r < RRPL) qe = jrev[r] ? rOF[r < RRPL ? r : 0] * qq : qq;
       sQ[qrow[r]] = qe;
     }
+    }
     wave_lds_sync();
 
     // net production omega = nu^T q_eff, sources, step size (Eqs 1-3)
@@ -578,8 +611,22 @@ stev_persistent(const KArgs a) {
           om += nu[e] * sQ[o];
         }
       } else {
+        // chunks of kCsrChunk: all loads of a chunk in flight together (the
+        // rows are padded to whole chunks with the zero entry)
         const int *jr = cj + kk[s] * dstride;
-        for (int e = 0; e < dmax; ++e) om += nu[e] * sQ[jr[e] * CPW + gi];
+        for (int e0 = 0; e0 < dmax; e0 += kCsrChunk) {
+          int jv[kCsrChunk];
+          R nv[kCsrChunk], qv[kCsrChunk];
+#pragma unroll
+          for (int u = 0; u < kCsrChunk; ++u) {
+            jv[u] = jr[e0 + u];
+            nv[u] = nu[e0 + u];
+          }
+#pragma unroll
+          for (int u = 0; u < kCsrChunk; ++u) qv[u] = sQ[jv[u] * CPW + gi];
+#pragma unroll
+          for (int u = 0; u < kCsrChunk; ++u) om += nv[u] * qv[u];
+        }
       }
       const R rk = Wk[s] * om * inv_rho;
       dYdt[s] = rk;

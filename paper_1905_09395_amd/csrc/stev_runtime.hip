@@ -224,7 +224,9 @@ static void pack_blob(const stev_mech *m, std::vector<unsigned char> &blob, Mech
   L.has_frac = m->has_frac;
   L.mixed_tmid = m->mixed_tmid;
   L.dmax = m->dmax;
-  L.dstride = m->dmax <= kCsrReg ? kCsrReg : m->dmax;
+  // rows padded (zero-rate entry, nu = 0) to the register walk's length, or
+  // to a multiple of the generic walk's chunk
+  L.dstride = m->dmax <= kCsrReg ? kCsrReg : (m->dmax + kCsrChunk - 1) / kCsrChunk * kCsrChunk;
   L.nnz_csr = (n_s + 1) * L.dstride;
   int off = 0;
   L.off_sp = off;   off = align16(off + (n_s + 1) * kSpStride * (int)sizeof(R));

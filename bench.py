@@ -37,6 +37,7 @@ METRIC = "cells/sec over one flow Δt, plain vs batched+MLP STEV; p50/p99 solve 
 PEAK = {"f64": 78.6, "f32": 157.3}   # TFLOP/s, MI355X vector FP64 / FP32
 KERNEL_SOURCES = ["paper_1905_09395_amd/csrc/stev_kernel.hip",
                   "paper_1905_09395_amd/csrc/stev_internal.h",
+                  "paper_1905_09395_amd/csrc/stev_thermo.h",
                   "paper_1905_09395_amd/csrc/stev_variants.h"]
 
 
@@ -143,12 +144,12 @@ def traffic_summary(fetch_csv, write_csv, precision, cells):
            "algorithmic_bytes_per_launch": algo,
            "kernel_sources_sha256": kernel_sources_sha(),
            "commands": [
-               "rocprofv3 --pmc FETCH_SIZE -d gpurun_out/pmc_fetch -o t --output-format csv "
-               f"-- python bench.py --probe --precision {precision}",
-               "rocprofv3 --pmc WRITE_SIZE -d gpurun_out/pmc_write -o t --output-format csv "
-               f"-- python bench.py --probe --precision {precision}",
-               "python bench.py --traffic-summary gpurun_out/pmc_fetch/t_counter_collection.csv "
-               f"gpurun_out/pmc_write/t_counter_collection.csv --precision {precision}"]}
+               f"rocprofv3 --pmc FETCH_SIZE -d gpurun_out/pmc_fetch_{precision} -o t "
+               f"--output-format csv -- python bench.py --probe --precision {precision}",
+               f"rocprofv3 --pmc WRITE_SIZE -d gpurun_out/pmc_write_{precision} -o t "
+               f"--output-format csv -- python bench.py --probe --precision {precision}",
+               f"python bench.py --traffic-summary gpurun_out/pmc_fetch_{precision}/t_counter_collection.csv "
+               f"gpurun_out/pmc_write_{precision}/t_counter_collection.csv --precision {precision}"]}
     base = os.path.join(ROOT, "profiles", f"stev_traffic_{precision}_mech19_{cells}")
     with open(base + ".json", "w") as f:
         json.dump(rec, f, indent=1)
@@ -167,6 +168,68 @@ def traffic_summary(fetch_csv, write_csv, precision, cells):
         f.write(f"| read + written per launch (MB) | {fetch_b / 1e6:.1f} + {write_b / 1e6:.1f} |\n")
         f.write(f"| algorithmic state bytes (MB) | {algo / 1e6:.1f} |\n")
     print(json.dumps(rec))
+
+
+def pmc_summary(csv_paths, precision, cells):
+    """Summarise rocprofv3 --pmc runs of `bench.py --probe` (counters of the
+    one integration launch) into profiles/stev_pmc_<prec>_mech19_<cells>.md."""
+    import csv
+    vals = {}
+    for path in csv_paths:
+        with open(path) as f:
+            for row in csv.DictReader(f):
+                if "stev_persistent" in row["Kernel_Name"]:
+                    vals[row["Counter_Name"]] = float(row["Counter_Value"])
+    base = os.path.join(ROOT, "profiles", f"stev_pmc_{precision}_mech19_{cells}")
+    with open(base + ".md", "w") as f:
+        f.write(f"# Counters of one stev_persistent launch ({precision}, 19 species, {cells} cells)\n\n")
+        f.write("Each counter set from its own run of:\n\n")
+        sets = {"f64": [("valu_f64", "SQ_INSTS_VALU_FLOPS_FP64 SQ_INSTS_VALU_FLOPS_FP64_TRANS "
+                                     "SQ_INSTS_VALU SQ_INSTS_VALU_FMA_F64 SQ_INSTS_VALU_ADD_F64 "
+                                     "SQ_INSTS_VALU_MUL_F64 SQ_INSTS_VALU_TRANS_F64 SQ_INSTS_LDS"),
+                        ("cyc_f64", "SQ_WAVE_CYCLES SQ_BUSY_CYCLES SQ_WAIT_ANY SQ_WAIT_INST_ANY "
+                                    "SQ_ACTIVE_INST_ANY SQ_ACTIVE_INST_VALU SQ_ACTIVE_INST_LDS "
+                                    "SQ_INSTS_SALU")],
+                "f32": [("valu_f32", "SQ_INSTS_VALU_FLOPS_FP32 SQ_INSTS_VALU_FLOPS_FP32_TRANS "
+                                     "SQ_INSTS_VALU SQ_INSTS_VALU_FMA_F32 SQ_INSTS_VALU_ADD_F32 "
+                                     "SQ_INSTS_VALU_MUL_F32 SQ_INSTS_VALU_TRANS_F32 SQ_INSTS_LDS")]}
+        for name, ctrs in sets[precision]:
+            f.write(f"    rocprofv3 --pmc {ctrs} -d gpurun_out/pmc_{name} -o t --output-format csv "
+                    f"-- python bench.py --probe --precision {precision}\n")
+        f.write("    python bench.py --pmc-summary " +
+                " ".join(f"gpurun_out/pmc_{name}/t_counter_collection.csv" for name, _ in sets[precision]) +
+                f" --precision {precision}\n\n")
+        f.write("| counter | value |\n|---|---|\n")
+        for k in sorted(vals):
+            f.write(f"| {k} | {vals[k]:.6g} |\n")
+        fl = "FP64" if precision == "f64" else "FP32"
+        key = f"SQ_INSTS_VALU_FLOPS_{fl}"
+        if key in vals:
+            f.write(f"\nCounted VALU FLOP per launch = 64 lanes x {key} "
+                    f"(ADD + MUL + 2 FMA + TRANS per wave instruction) = "
+                    f"{64 * vals[key]:.4g}; this counts every lane of every issued "
+                    f"instruction, idle lanes and software exp/log/divide included.\n")
+    rec = {"kernel": "stev_persistent", "precision": precision, "cells": cells,
+           "counters": vals, "kernel_sources_sha256": kernel_sources_sha()}
+    with open(base + ".json", "w") as f:
+        json.dump(rec, f, indent=1)
+    print(json.dumps(vals))
+
+
+def counted_flops(precision, cells):
+    """VALU FLOP per launch counted by rocprofv3 (64 lanes x ADD + MUL + 2 FMA
+    + TRANS instructions), from the committed counter record, or None when the
+    kernel sources changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"stev_pmc_{precision}_mech19_{cells}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("kernel_sources_sha256") != kernel_sources_sha():
+        return None
+    key = "SQ_INSTS_VALU_FLOPS_" + ("FP64" if precision == "f64" else "FP32")
+    v = rec["counters"].get(key)
+    return None if v is None else 64.0 * v
 
 
 def base_record(args, value, el, dtype, workload, **config):
@@ -360,8 +423,8 @@ def run_serve(args):
     mean_cells = 83879.0
     src = {6: synth.make_mech6(), 19: synth.make_mech19(), 53: synth.make_mech53()}
     # host-resident (pinned) request state staged through a device budget of
-    # 512 MiB, which the larger requests in flight together exceed
-    budget = 512 << 20
+    # 256 MiB, which the larger requests in flight together exceed
+    budget = 256 << 20
     ctx = stev.Context(0, hbm_budget=budget)
     mechs = {k: ctx.mechanism(m) for k, m in src.items()}
     for k, gm in mechs.items():
@@ -442,8 +505,8 @@ def run_serve(args):
         return lat, time.perf_counter() - start
 
     rows = {}
-    for load in (0.5, 0.8, 0.95):
-        at = arrivals(load)
+    for load in (0.5, 0.8, 0.95, "saturated"):
+        at = np.zeros(n_req) if load == "saturated" else arrivals(load)
         for _ in range(args.warmup):
             serve_run(at)
         ls, ms, bw = [], [], []
@@ -463,8 +526,8 @@ def run_serve(args):
     out = base_record(args, top["serve_cells_per_s"], float(np.sum(ms)), "f32",
                       "serving: Poisson arrivals, 32 requests of log-uniform size in "
                       "[1024, 524288] cells over 6-, 19- and 53-species mechanisms, FP32 + "
-                      "thermo network, host-resident pinned requests admitted by a 512 MiB HBM "
-                      "budget; value at load 0.95",
+                      "thermo network, host-resident pinned requests admitted by a 256 MiB HBM "
+                      "budget; value at load 0.95 ('saturated': every request at t=0)",
                       requests=n_req, cells=total, hbm_budget_bytes=budget,
                       plain_capacity_cells_per_s=cap, loads=rows)
     ctx.close()
@@ -485,9 +548,14 @@ def main():
     ap.add_argument("--workload", default="plain", choices=["plain", "batched", "mlp", "serve"])
     ap.add_argument("--traffic-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="CPU only: write the HBM traffic summary from two counter runs")
+    ap.add_argument("--pmc-summary", nargs="+", metavar="CSV",
+                    help="CPU only: summarise counter runs of the integration launch")
     args = ap.parse_args()
     if args.traffic_summary:
         traffic_summary(*args.traffic_summary, args.precision, args.cells)
+        return
+    if args.pmc_summary:
+        pmc_summary(args.pmc_summary, args.precision, args.cells)
         return
     if args.probe:
         args.steps, args.warmup, args.no_cpu = 1, 0, True
@@ -575,6 +643,10 @@ def main():
                      "kernel_ms": k_ms, "model_flop_per_cell_iter": flops_iter,
                      "transcendentals_per_cell_iter": transc},
     }
+    cflops = counted_flops(args.precision, n)
+    if cflops is not None:
+        out["roofline"]["counted_valu_tflops"] = cflops / (k_ms * 1e-3) / 1e12
+        out["roofline"]["counted_frac"] = out["roofline"]["counted_valu_tflops"] / peak
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(mech, T, P, Y, dt)
     gm.close()

@@ -44,14 +44,14 @@ class _Params(C.Structure):
     _fields_ = [("ystep_max", C.c_double), ("delta_max", C.c_double),
                 ("alpha", C.c_double), ("tol_ring", C.c_double),
                 ("tol_freq", C.c_double), ("r_fac", C.c_double),
-                ("rof_min", C.c_double), ("dft_window", C.c_int), ("pad_", C.c_int),
+                ("rof_min", C.c_double), ("dft_window", C.c_int), ("stab_limit", C.c_int),
                 ("max_iters", C.c_longlong), ("noise_eps", C.c_double),
                 ("noise_seed", C.c_ulonglong)]
 
 
 DEFAULT_PARAMS = dict(ystep_max=1e-3, delta_max=1e-2, alpha=1e-5, tol_ring=0.5,
                       tol_freq=1e-6, r_fac=2.0, rof_min=1e-12, dft_window=13,
-                      max_iters=1_000_000, noise_eps=0.0, noise_seed=0)
+                      stab_limit=0, max_iters=1_000_000, noise_eps=0.0, noise_seed=0)
 
 
 def lib():
@@ -66,6 +66,9 @@ def lib():
         L.orc_ystarstar.restype = C.c_double
         L.orc_source.argtypes = [C.POINTER(_Mech), C.POINTER(_Params), C.c_double, C.c_double,
                                  dp, dp, dp, dp, dp, dp, dp]
+        L.orc_jacobian_inf_norm.argtypes = [C.POINTER(_Mech), C.POINTER(_Params), C.c_double,
+                                            C.c_double, dp, dp, dp]
+        L.orc_jacobian_inf_norm.restype = C.c_double
         L.orc_step_size.argtypes = [C.POINTER(_Params), C.c_int, dp, dp, C.c_double, C.c_double]
         L.orc_step_size.restype = C.c_double
         L.orc_dft_mag.argtypes = [dp, C.c_int, dp]
@@ -129,7 +132,8 @@ def make_params(**kw):
     d = dict(DEFAULT_PARAMS)
     d.update(kw)
     return _Params(d["ystep_max"], d["delta_max"], d["alpha"], d["tol_ring"], d["tol_freq"],
-                   d["r_fac"], d["rof_min"], int(d["dft_window"]), 0, int(d["max_iters"]),
+                   d["r_fac"], d["rof_min"], int(d["dft_window"]), int(d["stab_limit"]),
+                   int(d["max_iters"]),
                    float(d["noise_eps"]), int(d["noise_seed"]))
 
 
@@ -156,6 +160,17 @@ def source(om, T, P, Y, rOF=None, **kw):
     lib().orc_source(C.byref(om.c), C.byref(prm), float(T), float(P), _p(Y), _p(rOF), _p(q),
                      _p(om_), _p(dY), _p(dT), _p(rho))
     return dict(q=q, omega=om_, dYdt=dY, dTdt=float(dT[0]), rho=float(rho[0]))
+
+
+def jacobian(om, T, P, Y, rOF=None, **kw):
+    """(A, ||A||_inf): d(dY/dt)/dY at fixed T and rho (Section 4, Eqs 22-24)."""
+    prm = make_params(**kw)
+    Y = np.ascontiguousarray(Y, dtype=np.float64)
+    rOF = np.ones(om.n_r) if rOF is None else np.ascontiguousarray(rOF, dtype=np.float64)
+    A = np.zeros((om.n_s, om.n_s))
+    nrm = lib().orc_jacobian_inf_norm(C.byref(om.c), C.byref(prm), float(T), float(P), _p(Y),
+                                      _p(rOF), _p(A))
+    return A, nrm
 
 
 def step_size(Y, dYdt, t, tf, **kw):

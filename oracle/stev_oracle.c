@@ -155,6 +155,84 @@ void orc_source_keyed(const orc_mech *m, const orc_params *p, double T, double P
   free(cp_R);
 }
 
+/* ---------------------------------------------------------------------------
+ * Section 4, Eqs 22-24: the Jacobian of the species equations and its
+ * infinity norm.  X = Y (mass fractions) at fixed T and rho:
+ *   dY_i/dt = (W_i / rho) sum_r nu_ir rOF_r q_r(C),  C_k = rho y**(Y_k) / W_k
+ *   A_ij    = (W_i / rho) sum_r nu_ir rOF_r [k_f dPf/dY_j - k_r dPr/dY_j]
+ * with P the side products prod C^o, whose factor for species j is
+ *   C_j^o = (rho / W_j)^o y**(Y_j)^o,
+ *   d(y**^o)/dY = o Y^(2o-1) (Y + 2 alpha) (alpha + Y)^-(1+o)   (Y > 0),
+ * and 0 for Y <= 0, where y** vanishes identically.
+ * ------------------------------------------------------------------------- */
+static double orc_dpow_dY(double Y, double rho, double W, double o, double alpha) {
+  if (!(Y > 0.0)) return 0.0;
+  return pow(rho / W, o) * o * pow(Y, 2.0 * o - 1.0) * (Y + 2.0 * alpha) *
+         pow(alpha + Y, -(1.0 + o));
+}
+
+double orc_jacobian_inf_norm(const orc_mech *m, const orc_params *p, double T, double P,
+                             const double *Y, const double *rOF, double *A_out) {
+  int n_s = m->n_s, n_r = m->n_r;
+  double *A = (double *)calloc((size_t)n_s * (size_t)n_s + 4 * (size_t)n_s, sizeof(double));
+  double *g = A + (size_t)n_s * n_s, *C = g + n_s;
+
+  double sumYW = 0.0;
+  for (int k = 0; k < n_s; ++k) sumYW += Y[k] / m->W[k];
+  double Wbar = 1.0 / sumYW;
+  double rho = P * Wbar / (ORC_R * T);
+  for (int k = 0; k < n_s; ++k) {
+    double th[3];
+    orc_thermo(m, k, T, th);
+    g[k] = th[1] - th[2];
+    C[k] = rho * orc_ystarstar(Y[k], p->alpha) / m->W[k];
+  }
+
+  for (int j = 0; j < n_r; ++j) {
+    int p0 = m->rxn_ptr[j], p1 = m->rxn_ptr[j + 1];
+    double m_f = 0.0;
+    for (int i = p0; i < p1; ++i)
+      if (m->nu[i] < 0.0) m_f += m->order[i];
+    double A_SI = m->A[j] * pow(1e-6, m_f - 1.0);
+    double kf = A_SI * pow(T, m->b[j]) * exp(-m->Ea[j] / (ORC_R * T));
+    double kr = 0.0;
+    if (m->rev[j]) {
+      double dG_RT = 0.0, dN = 0.0;
+      for (int i = p0; i < p1; ++i) {
+        dG_RT += m->nu[i] * g[m->sp_idx[i]];
+        dN += m->nu[i];
+      }
+      double K = pow(ORC_PATM / (ORC_R * T), dN) * exp(-dG_RT);
+      kr = kf / K;
+    }
+    double damp = m->rev[j] ? rOF[j] : 1.0;
+    /* d q_eff / dY_c for each participant c of this reaction */
+    for (int c = p0; c < p1; ++c) {
+      int forward = m->nu[c] < 0.0;
+      if (!forward && !m->rev[j]) continue;
+      int kc = m->sp_idx[c];
+      double d = orc_dpow_dY(Y[kc], rho, m->W[kc], m->order[c], p->alpha);
+      for (int i = p0; i < p1; ++i)   /* the other factors of the same side */
+        if (i != c && ((m->nu[i] < 0.0) == forward))
+          d *= pow(C[m->sp_idx[i]], m->order[i]);
+      double dq = forward ? kf * d : -kr * d;
+      for (int i = p0; i < p1; ++i) {
+        int ki = m->sp_idx[i];
+        A[(size_t)ki * n_s + kc] += m->W[ki] / rho * m->nu[i] * damp * dq;
+      }
+    }
+  }
+  double norm = 0.0;
+  for (int i = 0; i < n_s; ++i) {
+    double row = 0.0;
+    for (int c = 0; c < n_s; ++c) row += fabs(A[(size_t)i * n_s + c]);
+    if (row > norm) norm = row;
+  }
+  if (A_out) memcpy(A_out, A, sizeof(double) * (size_t)n_s * (size_t)n_s);
+  free(A);
+  return norm;
+}
+
 /* Section 2.1, Eqs 1-5, then h <= tf - t so the cell ends exactly at tf. */
 double orc_step_size(const orc_params *p, int n_s, const double *Y,
                      const double *dYdt, double t, double tf) {
@@ -282,6 +360,10 @@ int orc_integrate_cell_keyed(const orc_mech *m, const orc_params *p, double *T_i
       if (d < my) my = d;
     }
     double h = orc_step_size(p, n_s, Y, dYdt, t, tf);
+    if (p->stab_limit) {                                       /* Eq 25 */
+      double na = orc_jacobian_inf_norm(m, p, T, P, Y, rOF, NULL);
+      if (na > 0.0) h = fmin(h, 2.0 / na);
+    }
     double Tn = T + h * dTdt;                                  /* Eq 18 */
     int ok = isfinite(Tn) && isfinite(h);
     for (int k = 0; k < n_s; ++k) {

@@ -45,7 +45,7 @@ typedef struct {
   double r_fac;       /* Eq 12, > 1 */
   double rof_min;     /* floor keeping rOF > 0 */
   int dft_window;     /* Eq 8 ring length; 0 disables the DFT stabilisation */
-  int pad_;
+  int stab_limit;     /* Eq 25: also cap h at 2 / ||A||_inf (0 off, 1 on) */
   long long max_iters;
   /* Test instrument, not part of the method: when noise_eps > 0 every net
    * rate gets + noise_eps * max(q_f, q_r) * u, u uniform in [-1, 1) from a
@@ -69,6 +69,12 @@ void orc_source(const orc_mech *m, const orc_params *p, double T, double P,
 void orc_source_keyed(const orc_mech *m, const orc_params *p, double T, double P,
                       const double *Y, const double *rOF, double *q, double *omega,
                       double *dYdt, double *dTdt, double *rho, unsigned long long key);
+
+/* Section 4, Eqs 22-24: A = d(dY/dt)/dY at fixed T and rho for the rates the
+ * step uses (gamma-stabilised concentrations, rOF held fixed); returns
+ * ||A||_inf = max_i sum_j |A_ij|.  A (may be NULL) receives [n_s][n_s]. */
+double orc_jacobian_inf_norm(const orc_mech *m, const orc_params *p, double T, double P,
+                             const double *Y, const double *rOF, double *A);
 
 /* Eqs 1-5 plus the clamp to the end of the flow step. */
 double orc_step_size(const orc_params *p, int n_s, const double *Y,

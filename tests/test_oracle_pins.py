@@ -495,3 +495,107 @@ def test_adam_first_step_closed_form(orc):
     np.testing.assert_allclose(p, 1.0 - 0.01 * g / (np.abs(g) + 1e-8), rtol=1e-12)
     np.testing.assert_allclose(m1, 0.1 * g, rtol=1e-15)
     np.testing.assert_allclose(m2, 0.001 * g * g, rtol=1e-12)
+
+
+# ----------------------------------------------------------------------------
+# Section 4, Eqs 22-25: the Jacobian of the species equations (fixed T and
+# rho) and the stability cap h <= 2 / ||A||_inf
+# ----------------------------------------------------------------------------
+def test_jacobian_first_order_closed_form(orc):
+    k = 37.0
+    om = orc.OracleMech(tm.decay_ab(k))
+    A, nrm = orc.jacobian(om, 1000.0, P1, [0.3, 0.7], alpha=0.0)
+    # dY_A/dt = -k Y_A, dY_B/dt = +k Y_A (equal molar masses)
+    np.testing.assert_allclose(A, [[-k, 0.0], [k, 0.0]], rtol=1e-13, atol=0)
+    assert nrm == pytest.approx(k, rel=1e-13)
+
+
+def test_jacobian_gamma_factor_closed_form(orc):
+    k, alpha, y = 5.0, 1e-3, 2e-3
+    om = orc.OracleMech(tm.decay_ab(k))
+    A, _ = orc.jacobian(om, 1000.0, P1, [y, 1.0 - y], alpha=alpha)
+    # dY_A/dt = -k y^2/(alpha+y): derivative -k (y^2 + 2 alpha y)/(alpha+y)^2
+    d = -k * (y * y + 2 * alpha * y) / (alpha + y) ** 2
+    assert A[0, 0] == pytest.approx(d, rel=1e-13)
+    assert A[1, 0] == pytest.approx(-d, rel=1e-13)
+    # a depleted or negative species contributes nothing
+    A0, _ = orc.jacobian(om, 1000.0, P1, [-1e-9, 1.0], alpha=alpha)
+    assert np.all(A0 == 0.0)
+
+
+def test_jacobian_reversible_closed_form(orc):
+    kf, da7 = 3.0, 0.4
+    om = orc.OracleMech(tm.iso_ab(kf, 0.0, da7))
+    kr = kf / math.exp(da7)
+    rof = 0.25
+    A, nrm = orc.jacobian(om, 1200.0, P1, [0.6, 0.4], rOF=[rof], alpha=0.0)
+    np.testing.assert_allclose(A, rof * np.array([[-kf, kr], [kf, -kr]]), rtol=1e-12)
+    assert nrm == pytest.approx(rof * (kf + kr), rel=1e-12)
+
+
+def test_jacobian_second_order_closed_form(orc):
+    # 2 A -> 2 B, order 2: q = k C_A^2, dY_A/dt = -2 W k C_A^2 / rho = -2 k rho Y^2 / W
+    A_cgs, W, T, y = 3e7, 0.028, 900.0, 0.45
+    om = orc.OracleMech(tm.order_n(A_cgs, 2.0, nu=2.0, W=W))
+    rho = P1 * W / (R_SI * T)
+    k_si = A_cgs * 1e-6
+    A, _ = orc.jacobian(om, T, P1, [y, 1.0 - y], alpha=0.0)
+    assert A[0, 0] == pytest.approx(-4.0 * k_si * rho * y / W, rel=1e-12)
+
+
+def _fixed_rho_rhs(orc, om, T, P, Y, rOF, alpha):
+    """dY/dt at the density of state Y0 = Y (P rescaled so rho stays put)."""
+    return orc.source(om, T, P, Y, rOF=rOF, alpha=alpha)["dYdt"]
+
+
+def test_jacobian_matches_finite_differences(orc):
+    m = synth.make_mech19()
+    om = orc.OracleMech(m)
+    rng = np.random.default_rng(5)
+    W = np.asarray(m["W"])
+    for T in (1100.0, 1800.0, 2400.0):
+        Y = rng.dirichlet(np.ones(19))
+        rOF = rng.uniform(0.2, 1.0, m["n_r"])
+        A, nrm = orc.jacobian(om, T, P1, Y, rOF=rOF, alpha=1e-5)
+        s0 = np.sum(Y / W)
+        F = np.zeros_like(A)
+        for j in range(19):
+            hj = 1e-6 * Y[j]
+            cols = []
+            for sgn in (+1, -1):
+                Yp = Y.copy()
+                Yp[j] += sgn * hj
+                Pp = P1 * np.sum(Yp / W) / s0          # keeps rho fixed
+                cols.append(_fixed_rho_rhs(orc, om, T, Pp, Yp, rOF, 1e-5))
+            F[:, j] = (cols[0] - cols[1]) / (2 * hj)
+        scale = np.abs(A).max()
+        np.testing.assert_allclose(A, F, rtol=1e-5, atol=1e-7 * scale)
+        assert nrm == pytest.approx(np.abs(A).sum(axis=1).max(), rel=1e-14)
+        # Eq 24: ||A||_inf bounds the spectral radius
+        assert nrm >= np.abs(np.linalg.eigvals(A)).max() * (1 - 1e-12)
+
+
+def test_eq25_cap_holds_stiff_equilibrium_at_marginal_stability(orc):
+    """A <=> B near equilibrium: the net rates are tiny, so Eqs 1-5 allow the
+    full Delta t_max, where forward Euler diverges; with the Eq 25 cap every
+    step is 2/(kf + kr) and the deviation from equilibrium keeps its size,
+    alternating in sign (|1 - h (kf + kr)| = 1, Eq 19)."""
+    kf, da7 = 2.0e4, 0.3
+    om = orc.OracleMech(tm.iso_ab(kf, 0.0, da7))
+    K = math.exp(da7)
+    kr = kf / K
+    ya_eq = 1.0 / (K + 1.0)
+    dev = 1e-6
+    tf = 1e-2
+    kw = dict(alpha=0.0, ystep_max=1.0, delta_max=1e-2, dft_window=0)
+    free = orc.integrate_cell(om, 1000.0, P1, [ya_eq + dev, 1 - ya_eq - dev], tf, **kw)
+    assert abs(free["Y"][0] - ya_eq) > 1e3 * dev          # unstable without the cap
+    capped = orc.integrate_cell(om, 1000.0, P1, [ya_eq + dev, 1 - ya_eq - dev], tf,
+                                trace_cap=100000, stab_limit=1, **kw)
+    n = capped["iters"]
+    h = capped["h"][:n]
+    assert np.all(h[:-1] == pytest.approx(2.0 / (kf + kr), rel=1e-12))
+    # n - 1 full steps of factor -1, then the clamped last step h_l
+    h_l = h[-1]
+    expected = dev * (-1.0) ** (n - 1) * (1.0 - h_l * (kf + kr))
+    assert capped["Y"][0] - ya_eq == pytest.approx(expected, rel=1e-6, abs=1e-15)

@@ -86,6 +86,13 @@ typedef struct {
   int32_t use_graph;      /* stev_integrate_batched: record the launch
                              sequence as a HIP graph and replay it when an
                              identical call repeats (1), or launch directly (0) */
+  int32_t stab_limit;     /* Eq 25 (Sec 4): also cap every step at
+                             2 / ||A||_inf, A = d(dY/dt)/dY at fixed T and rho
+                             for the damped, gamma-stabilised rates (1), or
+                             not (0, default).  Needs 2*nu to be integers in
+                             [-127, 127] and thermo = STEV_THERMO_POLY,
+                             else STEV_EINVAL */
+  int32_t reserved;
 } stev_params;
 
 /* Per-call statistics. */

@@ -67,7 +67,18 @@ struct MechLayout {
   int off_rxi;         // i32 [n_r+1][kMaxPart] slot species: n_s = unit entry
   int off_cj;          // i32 [n_s+1][dstride]  reaction (packed order); n_r = zero entry
   int off_cnu;         // R   [n_s+1][dstride]  nu (0 on padding)
+  int jwidth;          // Jacobian pattern row length (multiple of kCsrChunk)
+  int off_jp;          // i32 [n_s+1][jwidth]   Jacobian pattern (see JP_* below)
 };
+
+// Jacobian pattern entry of species row i (Eq 25 limiter): the derivative
+// of reaction jn's damped rate with respect to the species in its rate-law
+// slot p is exchanged at slot index jn*kMaxPart + p; the entry carries that
+// index, 2 nu_i,jn as a signed byte, and a flag on the last entry of each
+// column (entries are grouped by column, i.e. by the slot's species).
+constexpr unsigned JP_IDX_MASK = 0xffffu;
+constexpr int JP_NU2_SHIFT = 16;
+constexpr unsigned JP_END = 0x80000000u;
 
 // Thermo network attached to a mechanism (Sec 3): 1 -> 32 -> 32 -> 2 n_s.
 // Its device blob (FP32 vectors, then bf16 hi/lo MFMA operand tiles) is
@@ -106,6 +117,10 @@ struct KArgs {
   int wave_bytes;          // per-wave LDS scratch
   int exch_bytes;          // of which the exchange rows (the rest: network scratch)
   int lds_mech_bytes;      // blob bytes staged (mechanism + network, aligned)
+  int mech_stage_bytes;    // of which the mechanism (the Jacobian pattern, last in
+                           // the blob, only for the Eq 25 limiter)
+  int jp_global;           // the Jacobian pattern is read from the blob in HBM
+                           // (it does not fit in LDS beside the rest)
   // cells
   long long n_cells;
   void *T;

@@ -111,6 +111,16 @@ __device__ __forceinline__ V grp_min(V v) {
   if constexpr (G >= 64) v = fmin(v, xchg<32>(v));
   return v;
 }
+template <int G, typename V>
+__device__ __forceinline__ V grp_max(V v) {
+  if constexpr (G >= 2) v = fmax(v, xchg<1>(v));
+  if constexpr (G >= 4) v = fmax(v, xchg<2>(v));
+  if constexpr (G >= 8) v = fmax(v, xchg<4>(v));
+  if constexpr (G >= 16) v = fmax(v, xchg<8>(v));
+  if constexpr (G >= 32) v = fmax(v, xchg<16>(v));
+  if constexpr (G >= 64) v = fmax(v, xchg<32>(v));
+  return v;
+}
 template <int G>
 __device__ __forceinline__ int grp_or(int v) {
   if constexpr (G >= 2) v |= xchg<1>(v);
@@ -192,7 +202,42 @@ __device__ __forceinline__ int find_batch(const KArgs &a, long long g) {
   return lo;
 }
 
-template <typename R, int G, int RPL, int RRPL, int SPL, int CSRR, bool MLP>
+// Eq 25 limiter: derivatives of one reaction's damped rate with respect to
+// the species of its rate-law slots, exchanged through sD.  C holds the slot
+// factors (C^o for a slot of order o), kf the forward rate constant, ek
+// 1/K_c, damp the reaction's rOF (1 if not reversible).
+template <typename R, int CPW>
+__device__ __forceinline__ void stab_slot_derivs(const R (&C)[kMaxPart], R kf, R ek, R damp,
+                                                 bool rev, bool has_frac, const R *rr,
+                                                 const int (&so)[kMaxPart], const R *sGu,
+                                                 const R *sLC, const R *sLG, R *sD, int jn,
+                                                 int gi) {
+  R g[kMaxPart];
+#pragma unroll
+  for (int p = 0; p < kMaxPart; ++p) {
+    g[p] = sGu[so[p]];
+    if (has_frac) {
+      // d(C^o)/dY = o exp(o ln C + ln((Y + 2 alpha) / (Y (alpha + Y)))): in
+      // logarithms, so that it keeps its finite limit where C^o and 1/Y
+      // leave the floating-point range (order 1/2 as Y -> 0)
+      const R o = rr[RX_ORD + p];
+      g[p] = (o != R(1)) ? o * Math<R>::ex(o * sLC[so[p]] + sLG[so[p]]) : g[p];
+    }
+  }
+  const R af = kf * damp;
+  const R ar = rev ? -(af * ek) : R(0);
+  R d[kMaxPart];
+  d[0] = af * (C[1] * C[2]) * g[0];
+  d[1] = af * (C[0] * C[2]) * g[1];
+  d[2] = af * (C[0] * C[1]) * g[2];
+  d[3] = ar * (C[4] * C[5]) * g[3];
+  d[4] = ar * (C[3] * C[5]) * g[4];
+  d[5] = ar * (C[3] * C[4]) * g[5];
+#pragma unroll
+  for (int p = 0; p < kMaxPart; ++p) sD[(jn * kMaxPart + p) * CPW + gi] = d[p];
+}
+
+template <typename R, int G, int RPL, int RRPL, int SPL, int CSRR, bool MLP, bool STAB>
 __global__ void __launch_bounds__(256)
 stev_persistent(const KArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -202,11 +247,11 @@ stev_persistent(const KArgs a) {
   {  // stage the packed mechanism (and the thermo network) into LDS
     const uint4 *src = reinterpret_cast<const uint4 *>(a.blob);
     uint4 *dst = reinterpret_cast<uint4 *>(smem);
-    const int n16 = a.L.bytes >> 4;
+    const int n16 = a.mech_stage_bytes >> 4;
     for (int i = threadIdx.x; i < n16; i += blockDim.x) dst[i] = src[i];
     if constexpr (MLP) {
       const uint4 *ws = reinterpret_cast<const uint4 *>(a.mlp.blob);
-      uint4 *wd = reinterpret_cast<uint4 *>(smem + a.L.bytes);
+      uint4 *wd = reinterpret_cast<uint4 *>(smem + a.mech_stage_bytes);
       for (int i = threadIdx.x; i < (a.mlp.L.bytes >> 4); i += blockDim.x) wd[i] = ws[i];
     }
   }
@@ -235,13 +280,30 @@ stev_persistent(const KArgs a) {
   R *sC = ws;
   R *sQ = sC + (n_s + 2) * CPW;
   R *sGb = sQ + (n_r + 2) * CPW;
+  //   with the Eq 25 limiter: sGu, sLC, sLG rows as sC (dC/dY factors, see
+  //   below) and sD, the derivative of each reaction's damped rate with
+  //   respect to the species of each rate-law slot, element
+  //   (jn * kMaxPart + p) * CPW + gi
+  R *sGu = sGb + (mixed ? (n_s + 2) * CPW : 0);
+  R *sLC = sGu + (n_s + 2) * CPW;
+  R *sLG = sLC + (n_s + 2) * CPW;
+  R *sD = sLG + (n_s + 2) * CPW;
   if (l == 0) {
     sC[n_s * CPW + gi] = R(1);
     sQ[n_r * CPW + gi] = R(0);
     if (mixed) sGb[n_s * CPW + gi] = R(0);
+    if constexpr (STAB) {
+      sGu[n_s * CPW + gi] = R(0);
+      sLC[n_s * CPW + gi] = R(-INFINITY);
+      sLG[n_s * CPW + gi] = R(0);
+    }
   }
+  const unsigned *jpt = a.jp_global
+                            ? reinterpret_cast<const unsigned *>(
+                                  reinterpret_cast<const unsigned char *>(a.blob) + a.L.off_jp)
+                            : reinterpret_cast<const unsigned *>(smem + a.L.off_jp);
   // thermo-network scratch: layer activations (bf16 hi/lo planes) and outputs
-  const unsigned char *wnet = smem + a.L.bytes;
+  const unsigned char *wnet = smem + a.mech_stage_bytes;
   __bf16 *act1 = reinterpret_cast<__bf16 *>(reinterpret_cast<unsigned char *>(ws) + a.exch_bytes);
   __bf16 *act2 = act1 + 2 * NT * 16 * kMlpH;
   float *mout = reinterpret_cast<float *>(act2 + 2 * NT * 16 * kMlpH);
@@ -506,6 +568,18 @@ stev_persistent(const KArgs a) {
       const R yp = Y[s] > R(0) ? Y[s] : R(0);
       const R yss = yp * yp / (alpha + yp);                          // Eqs 6-7
       sC[crow[s]] = (yp > R(0)) ? rho * yss * invW[s] : R(0);
+      if constexpr (STAB) {
+        // dC/dY = (rho / W) Y (Y + 2 alpha) / (alpha + Y)^2; for slots of
+        // order o != 1 the logarithms ln C and ln((Y + 2 alpha)/(Y (alpha + Y)));
+        // everything vanishes for Y <= 0, where C does
+        const R den = alpha + yp;
+        sGu[crow[s]] = (yp > R(0)) ? rho * invW[s] * (yp * (yp + R(2) * alpha)) / (den * den) : R(0);
+        if (has_frac) {
+          const R ly = Math<R>::lg(yp), la = Math<R>::lg(den);
+          sLC[crow[s]] = (yp > R(0)) ? Math<R>::lg(rho * invW[s]) + R(2) * ly - la : R(-INFINITY);
+          sLG[crow[s]] = (yp > R(0)) ? Math<R>::lg(yp + R(2) * alpha) - ly - la : R(0);
+        }
+      }
     }
     wave_lds_sync();
 
@@ -541,6 +615,11 @@ stev_persistent(const KArgs a) {
         R qe = qq;
         if (r < RRPL) qe = jrev[r] ? rOF[r < RRPL ? r : 0] * qq : qq;
         sQ[qrow[r]] = qe;
+        if constexpr (STAB) {
+          const R damp = (r < RRPL && jrev[r]) ? rOF[r < RRPL ? r : 0] : R(1);
+          stab_slot_derivs<R, CPW>(C, kf, ek, damp, jrev[r], false, rr, soff[r], sGu, sLC, sLG,
+                                   sD, jj[r], gi);
+        }
       }
     } else {
 #pragma unroll
@@ -565,8 +644,8 @@ stev_persistent(const KArgs a) {
       }
       const R pf = C[0] * C[1] * C[2];
       R qq = kf * pf;
+      R ek = R(0);   // 1 / K_c
       if (n_rev > 0) {
-        R ek;   // 1 / K_c
         if (kEarly && !mixed) {
           ek = ek_e[r < RPL ? r : 0];
         } else {
@@ -590,6 +669,11 @@ stev_persistent(const KArgs a) {
       R qe = qq;
       if (r < RRPL) qe = jrev[r] ? rOF[r < RRPL ? r : 0] * qq : qq;
       sQ[qrow[r]] = qe;
+      if constexpr (STAB) {
+        const R damp = (r < RRPL && jrev[r]) ? rOF[r < RRPL ? r : 0] : R(1);
+        stab_slot_derivs<R, CPW>(C, kf, ek, damp, jrev[r], has_frac, rr, soff[r], sGu, sLC,
+                                 sLG, sD, jj[r], gi);
+      }
     }
     }
     wave_lds_sync();
@@ -635,11 +719,43 @@ stev_persistent(const KArgs a) {
       const R ystar = (Y[s] < R(1e-20)) ? R(1) : R(0.9) * Y[s];  // Eq 2
       tst = fmin(tst, fmin(ystep, ystar) / rstar);               // Eq 3
     }
+    // Eq 25: ||A||_inf of A = d(dY/dt)/dY at fixed T and rho.  Row i walks
+    // its pattern: per column, the sum of nu_i,jn * d(q_eff,jn)/dY_j over the
+    // reactions sharing i and j, then |.| summed over the columns
+    R normA = R(0);
+    if constexpr (STAB) {
+#pragma unroll
+      for (int s = 0; s < SPL; ++s) {
+        const unsigned *je = jpt + kk[s] * a.L.jwidth;
+        R row = R(0), acc = R(0);
+        for (int e0 = 0; e0 < a.L.jwidth; e0 += kCsrChunk) {
+          unsigned ev[kCsrChunk];
+          R dv[kCsrChunk];
+#pragma unroll
+          for (int u = 0; u < kCsrChunk; ++u) ev[u] = je[e0 + u];
+#pragma unroll
+          for (int u = 0; u < kCsrChunk; ++u) dv[u] = sD[(int)(ev[u] & JP_IDX_MASK) * CPW + gi];
+#pragma unroll
+          for (int u = 0; u < kCsrChunk; ++u) {
+            const int nu2 = ((int)(ev[u] << 8)) >> 24;   // 2 nu, signed byte
+            acc += R(nu2) * dv[u];
+            const bool end = (ev[u] & JP_END) != 0u;
+            row = end ? row + fabs(acc) : row;
+            acc = end ? R(0) : acc;
+          }
+        }
+        normA = fmax(normA, R(0.5) * row * Wk[s] * inv_rho);
+      }
+      normA = grp_max<G>(normA);
+    }
     sum_hw = grp_sum<G>(sum_hw);
     tst = grp_min<G>(tst);
     const R dTdt = -T * sum_hw * inv_rho / sumYcp;
     double h = fmin((double)tst, dtmax);   // Eqs 4-5
     h = fmin(h, tf - t);
+    if constexpr (STAB) {
+      if (normA > R(0)) h = fmin(h, 2.0 / (double)normA);   // Eq 25
+    }
     if (!run) h = 0.0;
     const R hR = R(h);
 
@@ -727,15 +843,17 @@ __global__ void stev_zero_u64(unsigned long long *p, int n) {
 
 namespace stev {
 
-#define STEV_INST(R, G, RPL, RRPL, SPL, CSRR) \
-  reinterpret_cast<const void *>(&stev_persistent<R, G, RPL, RRPL, SPL, CSRR, false>)
+#define STEV_INST(R, G, RPL, RRPL, SPL, CSRR, STAB) \
+  reinterpret_cast<const void *>(&stev_persistent<R, G, RPL, RRPL, SPL, CSRR, false, STAB>)
 #define STEV_INST_MLP(G, RPL, RRPL, SPL, CSRR) \
-  reinterpret_cast<const void *>(&stev_persistent<float, G, RPL, RRPL, SPL, CSRR, true>)
+  reinterpret_cast<const void *>(&stev_persistent<float, G, RPL, RRPL, SPL, CSRR, true, false>)
 
 const VariantInfo kVariants[] = {
-#define STEV_VARIANT(G, RPL, RRPL, SPL, CSRR)                               \
-  {G, RPL, RRPL, SPL, CSRR, STEV_INST(double, G, RPL, RRPL, SPL, CSRR), \
-   STEV_INST(float, G, RPL, RRPL, SPL, CSRR)},
+#define STEV_VARIANT(G, RPL, RRPL, SPL, CSRR)                                      \
+  {G, RPL, RRPL, SPL, CSRR, STEV_INST(double, G, RPL, RRPL, SPL, CSRR, false),   \
+   STEV_INST(float, G, RPL, RRPL, SPL, CSRR, false),                             \
+   STEV_INST(double, G, RPL, RRPL, SPL, CSRR, true),                             \
+   STEV_INST(float, G, RPL, RRPL, SPL, CSRR, true)},
     STEV_VARIANT_LIST
 #undef STEV_VARIANT
 };

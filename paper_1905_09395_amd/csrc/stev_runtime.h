@@ -61,6 +61,9 @@ struct stev_mech {
   std::vector<int> orig_of_new;
   std::vector<int> csr_ptr, csr_j;
   std::vector<double> csr_nu;
+  std::vector<unsigned> jp;          // Jacobian pattern, [n_s + 1][jwidth]
+  int jwidth = 8;
+  int jac_ok = 1;                    // every 2 nu fits a signed byte exactly
   void *blob[2] = {nullptr, nullptr};
   size_t blob_bytes[2] = {0, 0};
   stev::MechLayout L[2];
@@ -74,6 +77,8 @@ struct stev_mech {
 struct LaunchPlan {
   int variant = -1, G = 1, waves = 8, block = 512, grid = 1, lds = 0, wave_bytes = 0, exch_bytes = 0;
   int occ = 1, compact = 1;
+  int stage_bytes = 0;   // mechanism bytes staged into LDS
+  int jp_global = 0;     // Eq 25 limiter: pattern read from HBM
   const void *fn = nullptr;
 };
 

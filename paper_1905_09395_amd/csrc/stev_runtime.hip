@@ -234,6 +234,8 @@ static void pack_blob(const stev_mech *m, std::vector<unsigned char> &blob, Mech
   L.off_rxi = off;  off = align16(off + (n_r + 1) * kMaxPart * 4);
   L.off_cj = off;   off = align16(off + L.nnz_csr * 4);
   L.off_cnu = off;  off = align16(off + L.nnz_csr * (int)sizeof(R));
+  L.jwidth = m->jwidth;
+  L.off_jp = off;   off = align16(off + (n_s + 1) * m->jwidth * 4);
   L.bytes = std::max(off, 16);
   blob.assign(L.bytes, 0);
   R *sp = reinterpret_cast<R *>(blob.data() + L.off_sp);
@@ -300,6 +302,48 @@ static void pack_blob(const stev_mech *m, std::vector<unsigned char> &blob, Mech
       cnu[k * L.dstride + e] = used ? (R)m->csr_nu[m->csr_ptr[k] + e] : (R)0;
     }
   }
+  std::memcpy(blob.data() + L.off_jp, m->jp.data(), m->jp.size() * 4);
+}
+
+// Jacobian pattern (Eq 25 limiter): for species i, every (reaction, rate-law
+// slot) pair whose slot species j is a real species and whose rate depends on
+// it, with nu_ij; grouped by column j (ascending), reactions in original
+// order inside a column.  Rows are padded with entries on the dummy
+// reaction's zero slot.
+static void build_jacobian_pattern(stev_mech *m) {
+  const int n_s = m->n_s, n_r = m->n_r;
+  struct E { int col, idx, nu2; };
+  std::vector<std::vector<E>> rows(n_s);
+  m->jac_ok = 1;
+  for (int i = 0; i < n_s; ++i) {
+    for (int e = m->csr_ptr[i]; e < m->csr_ptr[i + 1]; ++e) {
+      const int jn = m->csr_j[e];
+      const double nu2 = 2.0 * m->csr_nu[e];
+      if (nu2 != std::nearbyint(nu2) || std::fabs(nu2) > 127.0) m->jac_ok = 0;
+      const auto &P = m->rx[jn];
+      for (int p = 0; p < kMaxPart; ++p) {
+        const int j = P.slot_sp[p];
+        if (j < 0) continue;
+        if (p >= kHalfPart && !P.rev) continue;   // no reverse rate
+        rows[i].push_back({j, jn * kMaxPart + p, (int)std::nearbyint(nu2)});
+      }
+    }
+    std::stable_sort(rows[i].begin(), rows[i].end(),
+                     [](const E &a, const E &b) { return a.col < b.col; });
+  }
+  size_t w = 1;
+  for (auto &r : rows) w = std::max(w, r.size());
+  m->jwidth = (int)((w + kCsrChunk - 1) / kCsrChunk * kCsrChunk);
+  const unsigned zero = (unsigned)(n_r * kMaxPart) | JP_END;   // dummy reaction: rate 0
+  m->jp.assign((size_t)(n_s + 1) * m->jwidth, zero);
+  for (int i = 0; i < n_s; ++i)
+    for (size_t q = 0; q < rows[i].size(); ++q) {
+      const E &x = rows[i][q];
+      const bool end = q + 1 == rows[i].size() || rows[i][q + 1].col != x.col;
+      m->jp[(size_t)i * m->jwidth + q] = (unsigned)x.idx |
+                                         ((unsigned)(x.nu2 & 0xff) << JP_NU2_SHIFT) |
+                                         (end ? JP_END : 0u);
+    }
 }
 
 extern "C" int stev_create_mechanism(stev_ctx *ctx, const stev_mech_desc *d, stev_mech **out) {
@@ -456,6 +500,7 @@ extern "C" int stev_create_mechanism(stev_ctx *ctx, const stev_mech_desc *d, ste
       m->csr_nu.push_back(e.second);
     }
   }
+  build_jacobian_pattern(m);
   // device blobs
   (void)hipSetDevice(ctx->device);
   for (int prec = 0; prec < 2; ++prec) {
@@ -554,7 +599,8 @@ int fill_kargs(stev_ctx *ctx, const stev_mech *m, const stev_params &p, double d
   const int prec = p.precision;
   a.blob = m->blob[prec];
   a.L = m->L[prec];
-  a.lds_mech_bytes = a.L.bytes;
+  a.mech_stage_bytes = a.L.off_jp;   // set per launch plan by launch_stev
+  a.lds_mech_bytes = a.mech_stage_bytes;
   a.tf = dt_flow;
   a.dtmax = dt_flow * p.delta_max;
   a.ystep = p.ystep_max;
@@ -597,6 +643,13 @@ int validate_params(stev_ctx *ctx, const stev_mech *m, const stev_params &p, dou
     return stev_fail(ctx, STEV_EINVAL, "lanes_per_cell out of range");
   if (p.thermo == STEV_THERMO_MLP && !m->mlp.enabled)
     return stev_fail(ctx, STEV_EINVAL, "thermo=MLP but no network attached to the mechanism");
+  if (p.stab_limit != 0 && p.stab_limit != 1)
+    return stev_fail(ctx, STEV_EINVAL, "stab_limit must be 0 or 1");
+  if (p.stab_limit && p.thermo != STEV_THERMO_POLY)
+    return stev_fail(ctx, STEV_EINVAL, "the Eq 25 limiter runs with the polynomial thermo");
+  if (p.stab_limit && !m->jac_ok)
+    return stev_fail(ctx, STEV_EINVAL,
+                     "the Eq 25 limiter needs every 2*nu to be an integer in [-127, 127]");
   return STEV_OK;
 }
 
@@ -609,7 +662,8 @@ int plan_launch(stev_ctx *ctx, const stev_mech *m, const stev_params &p, long lo
   const VariantInfo &V = kVariants[v];
   lp.variant = v;
   lp.G = V.G;
-  lp.fn = p.precision == STEV_F64 ? V.fn_f64 : V.fn_f32;
+  lp.fn = p.precision == STEV_F64 ? (p.stab_limit ? V.fn_f64_stab : V.fn_f64)
+                                  : (p.stab_limit ? V.fn_f32_stab : V.fn_f32);
   if (p.thermo == STEV_THERMO_MLP) {
     if (p.precision != STEV_F32)
       return stev_fail(ctx, STEV_EINVAL, "the thermo network runs with FP32 state (precision=STEV_F32)");
@@ -617,10 +671,17 @@ int plan_launch(stev_ctx *ctx, const stev_mech *m, const stev_params &p, long lo
   }
   const int rsz = p.precision == STEV_F64 ? 8 : 4;
   const int cpw = 64 / V.G;
-  lp.exch_bytes = align16((m->n_s + 2 + m->n_r + 2 + (m->mixed_tmid ? m->n_s + 2 : 0)) * cpw * rsz);
+  const int stab_rows = p.stab_limit ? 3 * (m->n_s + 2) + kMaxPart * (m->n_r + 1) : 0;
+  lp.exch_bytes = align16((m->n_s + 2 + m->n_r + 2 + (m->mixed_tmid ? m->n_s + 2 : 0) + stab_rows) *
+                          cpw * rsz);
   lp.wave_bytes = lp.exch_bytes + mlp_wave_bytes(m, p, V.G);
-  const int mech_bytes = m->L[p.precision].bytes +
-                         (p.thermo == STEV_THERMO_MLP ? m->mlp.dev.L.bytes : 0);
+  // the Jacobian pattern (last in the blob) is staged only for the Eq 25
+  // limiter, and read from HBM when it would not leave room for one wave
+  const MechLayout &ML = m->L[p.precision];
+  const int net_bytes = p.thermo == STEV_THERMO_MLP ? m->mlp.dev.L.bytes : 0;
+  lp.jp_global = p.stab_limit && ML.bytes + net_bytes + lp.wave_bytes > ctx->max_lds;
+  lp.stage_bytes = (p.stab_limit && !lp.jp_global) ? ML.bytes : ML.off_jp;
+  const int mech_bytes = lp.stage_bytes + net_bytes;
   int waves = p.waves_per_wg > 0 ? p.waves_per_wg : 4;
   while (waves > 1 && mech_bytes + waves * lp.wave_bytes > ctx->max_lds) --waves;
   lp.lds = mech_bytes + waves * lp.wave_bytes;
@@ -655,7 +716,9 @@ int launch_zero(stev_ctx *ctx, unsigned long long *p, int n, hipStream_t s) {
 int launch_stev(stev_ctx *ctx, const LaunchPlan &lp, KArgs &a, hipStream_t s) {
   a.wave_bytes = lp.wave_bytes;
   a.exch_bytes = lp.exch_bytes;
-  a.lds_mech_bytes = a.L.bytes + (a.mlp.enabled ? a.mlp.L.bytes : 0);
+  a.mech_stage_bytes = lp.stage_bytes;
+  a.jp_global = lp.jp_global;
+  a.lds_mech_bytes = a.mech_stage_bytes + (a.mlp.enabled ? a.mlp.L.bytes : 0);
   void *args[] = {&a};
   HIP_TRY(hipLaunchKernel(lp.fn, dim3(lp.grid), dim3(lp.block), args, lp.lds, s));
   return STEV_OK;

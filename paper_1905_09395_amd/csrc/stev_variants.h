@@ -20,6 +20,8 @@ struct VariantInfo {
   int G, RPL, RRPL, SPL, CSRR;
   const void *fn_f64;
   const void *fn_f32;
+  const void *fn_f64_stab;   // with the Eq 25 step cap
+  const void *fn_f32_stab;
 };
 
 extern const VariantInfo kVariants[];

@@ -554,6 +554,8 @@ def main():
     ap.add_argument("--precision", default="f64", choices=["f64", "f32"])
     ap.add_argument("--cells", type=int, default=262144)
     ap.add_argument("--lanes", type=int, default=0)
+    ap.add_argument("--stab", action="store_true",
+                    help="plain workload with the Eq 25 step cap (2/||A||_inf)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--probe", action="store_true",
                     help="counter-calibration run: one plain copy, then one step")
@@ -603,7 +605,8 @@ def main():
     P0 = torch.tensor(P, dtype=dtype, device=dev)
     Y0 = torch.tensor(Y, dtype=dtype, device=dev).contiguous()
     Tw, Yw = T0.clone(), Y0.clone()
-    prm = stev.default_params(precision=prec, lanes_per_cell=args.lanes)
+    prm = stev.default_params(precision=prec, lanes_per_cell=args.lanes,
+                              stab_limit=1 if args.stab else 0)
 
     def step():
         Tw.copy_(T0)
@@ -644,7 +647,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"plain STEV, 19-species/50-reversible-reaction synthetic "
                                f"mechanism, {n} cells (70% 300-900 K, 30% 1400-2500 K), "
-                               f"dt_flow=1e-4 s, {args.precision}",
+                               f"dt_flow=1e-4 s, {args.precision}" +
+                               (", every step also capped at 2/||A||_inf (Eq 25)"
+                                if args.stab else ""),
                    "cells": n, "dt_flow": dt, "lanes_per_cell": st["lanes_per_cell"],
                    "waves_per_wg": st["waves_per_wg"], "grid_wgs": st["grid_wgs"],
                    "cell_iterations_per_step": int(np.mean(iters)),

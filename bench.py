@@ -660,6 +660,22 @@ def main():
                      "kernel_ms": k_ms, "model_flop_per_cell_iter": flops_iter,
                      "transcendentals_per_cell_iter": transc},
     }
+    # end to end with host-resident (pinned) arrays: PCIe copies in and out
+    # included; a side figure, never `value`
+    if not args.probe:
+        Th = torch.tensor(T, dtype=dtype).pin_memory()
+        Ph = torch.tensor(P, dtype=dtype).pin_memory()
+        Yh = torch.tensor(Y, dtype=dtype).contiguous().pin_memory()
+        Th2, Yh2 = Th.clone().pin_memory(), Yh.clone().pin_memory()
+        ctx.integrate(gm, Th2, Ph, Yh2, dt, params=prm)       # staging buffers
+        e2e = []
+        for _ in range(2):
+            Th2.copy_(Th)
+            Yh2.copy_(Yh)
+            t1 = time.perf_counter()
+            ctx.integrate(gm, Th2, Ph, Yh2, dt, params=prm)
+            e2e.append(time.perf_counter() - t1)
+        out["config"]["host_arrays_cells_per_s"] = n / min(e2e)
     cflops = counted_flops(args.precision, n)
     if cflops is not None:
         out["roofline"]["counted_valu_tflops"] = cflops / (k_ms * 1e-3) / 1e12

@@ -92,6 +92,14 @@ typedef struct {
                              not (0, default).  Needs 2*nu to be integers in
                              [-127, 127] and thermo = STEV_THERMO_POLY,
                              else STEV_EINVAL */
+  int32_t hot_first;      /* stev_integrate: hand cells to the workgroups
+                             hottest first (1, default) or in array order
+                             (0).  Igniting cells take the most steps and the
+                             longest of them sets the time of a field; the
+                             order changes scheduling only, never a cell's
+                             result.  Fields under 4096 cells keep array
+                             order; the order takes 4 * n_cells + 512 bytes
+                             of the context's device scratch */
   int32_t reserved;
 } stev_params;
 
@@ -101,7 +109,8 @@ typedef struct {
   int64_t total_iters;    /* sum over cells of iterations */
   int64_t max_cell_iters;
   int64_t n_failed;       /* cells with status != 0 */
-  double kernel_ms;       /* HIP-event time of the integration launch(es) */
+  double kernel_ms;       /* HIP-event time of the integration launch(es),
+                             the hottest-first ordering pass included */
   double total_ms;        /* wall time inside the call (incl. copies) */
   int32_t lanes_per_cell; /* variant actually used */
   int32_t waves_per_wg;

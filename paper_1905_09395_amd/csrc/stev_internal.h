@@ -143,6 +143,9 @@ struct KArgs {
   const BatchDesc *batches;
   unsigned long long *bstats;
   int n_batches;
+  // single batch only: the launch's i-th cell is cell cell_index[i] of the
+  // arrays (nullptr: cell i); the dispatch order of a field
+  const int *cell_index;
   MlpDev mlp;
 };
 

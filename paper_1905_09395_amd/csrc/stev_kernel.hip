@@ -428,7 +428,7 @@ stev_persistent(const KArgs a) {
           const long long g = (long long)base + rank;
           if (g < a.n_cells) {
             cb = a.batches ? find_batch(a, g) : -1;
-            cell = a.batches ? g - a.batches[cb].begin : g;
+            cell = a.batches ? g - a.batches[cb].begin : (a.cell_index ? a.cell_index[g] : g);
             const CellRef<R> cr = cell_ref<R>(a, cb, cell);
             T = *cr.T;
             P = *cr.P;
@@ -834,6 +834,73 @@ __global__ void stev_zero_u64(unsigned long long *p, int n) {
   if (i < n) p[i] = 0ull;
 }
 
+// Dispatch order, hottest cells first (igniting cells take the most steps and
+// the longest of them sets the time of a field): cells are bucketed by
+// temperature into kOrderBuckets bins of kOrderBinK kelvin, and the bins are
+// laid out from the hottest down.  Pass 1 counts the bins, pass 2 turns the
+// counts into descending-order offsets (one block), pass 3 places each cell;
+// the order inside a bin is that of the atomics, and a cell's result does not
+// depend on it.
+constexpr int kOrderBuckets = 64;
+constexpr double kOrderBinK = 75.0;
+
+template <typename R>
+__device__ __forceinline__ int order_bin(R T) {
+  const double b = (double)T / kOrderBinK;
+  const int k = (b >= 0.0) ? (int)b : 0;   // NaN and negatives: bin 0
+  return k < kOrderBuckets - 1 ? k : kOrderBuckets - 1;
+}
+
+template <typename R>
+__global__ void stev_order_count(const R *T, long long n, unsigned long long *cnt) {
+  __shared__ unsigned int h[kOrderBuckets];
+  for (int i = threadIdx.x; i < kOrderBuckets; i += blockDim.x) h[i] = 0u;
+  __syncthreads();
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    atomicAdd(&h[order_bin(T[i])], 1u);
+  __syncthreads();
+  for (int i = threadIdx.x; i < kOrderBuckets; i += blockDim.x)
+    if (h[i]) atomicAdd(&cnt[i], (unsigned long long)h[i]);
+}
+
+// cnt[b] -> start of bin b in the hottest-first order (single thread block)
+__global__ void stev_order_offsets(unsigned long long *cnt) {
+  if (threadIdx.x == 0) {
+    unsigned long long run = 0;
+    for (int b = kOrderBuckets - 1; b >= 0; --b) {
+      const unsigned long long c = cnt[b];
+      cnt[b] = run;
+      run += c;
+    }
+  }
+}
+
+template <typename R>
+__global__ void stev_order_place(const R *T, long long n, unsigned long long *next, int *idx) {
+  // each block places one contiguous chunk: it counts its chunk per bin in
+  // LDS, reserves its range of every bin with one global atomic, then hands
+  // out places inside the range with LDS atomics
+  __shared__ unsigned int h[kOrderBuckets];
+  __shared__ unsigned long long base[kOrderBuckets];
+  const long long chunk = (n + gridDim.x - 1) / gridDim.x;
+  const long long lo = (long long)blockIdx.x * chunk;
+  const long long hi = lo + chunk < n ? lo + chunk : n;
+  for (int i = threadIdx.x; i < kOrderBuckets; i += blockDim.x) h[i] = 0u;
+  __syncthreads();
+  for (long long i = lo + threadIdx.x; i < hi; i += blockDim.x) atomicAdd(&h[order_bin(T[i])], 1u);
+  __syncthreads();
+  for (int i = threadIdx.x; i < kOrderBuckets; i += blockDim.x) {
+    base[i] = h[i] ? atomicAdd(&next[i], (unsigned long long)h[i]) : 0ull;
+    h[i] = 0u;
+  }
+  __syncthreads();
+  for (long long i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+    const int b = order_bin(T[i]);
+    idx[base[b] + atomicAdd(&h[b], 1u)] = (int)i;
+  }
+}
+
 }  // namespace stev
 
 // ---------------------------------------------------------------------------
@@ -866,5 +933,10 @@ const void *const kMlpVariants[] = {
 #undef STEV_VARIANT
 };
 const void *kZeroKernel = reinterpret_cast<const void *>(&stev_zero_u64);
+const void *kOrderCount[2] = {reinterpret_cast<const void *>(&stev_order_count<double>),
+                              reinterpret_cast<const void *>(&stev_order_count<float>)};
+const void *kOrderOffsets = reinterpret_cast<const void *>(&stev_order_offsets);
+const void *kOrderPlace[2] = {reinterpret_cast<const void *>(&stev_order_place<double>),
+                              reinterpret_cast<const void *>(&stev_order_place<float>)};
 
 }  // namespace stev

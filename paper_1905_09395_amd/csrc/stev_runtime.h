@@ -145,7 +145,7 @@ struct stev_ctx {
   std::string err;
   unsigned long long *ctl = nullptr;       // device control words
   unsigned long long *ctl_host = nullptr;  // pinned mirror
-  Scratch sT, sP, sY, sI, sS;
+  Scratch sT, sP, sY, sI, sS, sIdx;
   ServeState *serve = nullptr;
   std::map<std::string, stev_params> tune_cache;
   // multi-batch launches: side streams for mechanism groups, fork/join events
@@ -157,6 +157,9 @@ struct stev_ctx {
   std::map<std::string, MultiLaunch *> plans;
   uint64_t plan_clock = 0;
 };
+
+// fields smaller than this keep array order (hot_first)
+constexpr long long kOrderMinCells = 4096;
 
 int stev_fail(stev_ctx *ctx, int code, const char *fmt, ...);
 int dev_alloc(stev_ctx *ctx, void **p, size_t bytes);

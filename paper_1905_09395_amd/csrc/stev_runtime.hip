@@ -121,6 +121,7 @@ extern "C" void stev_default_params(stev_params *p) {
   p->compact_every = 0;
   p->grid_wgs = 0;
   p->use_graph = 1;
+  p->hot_first = 1;
 }
 
 extern "C" int stev_init(stev_ctx **out, int hip_device, size_t hbm_budget_bytes) {
@@ -201,7 +202,7 @@ extern "C" void stev_shutdown(stev_ctx *ctx) {
     if (ctx->ev_join[i]) (void)hipEventDestroy(ctx->ev_join[i]);
   }
   if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
-  for (auto *s : {&ctx->sT, &ctx->sP, &ctx->sY, &ctx->sI, &ctx->sS}) s->release(ctx);
+  for (auto *s : {&ctx->sT, &ctx->sP, &ctx->sY, &ctx->sI, &ctx->sS, &ctx->sIdx}) s->release(ctx);
   dev_free(ctx, ctx->ctl, 64 * sizeof(unsigned long long));
   if (ctx->ctl_host) (void)hipHostFree(ctx->ctl_host);
   if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
@@ -643,6 +644,8 @@ int validate_params(stev_ctx *ctx, const stev_mech *m, const stev_params &p, dou
     return stev_fail(ctx, STEV_EINVAL, "lanes_per_cell out of range");
   if (p.thermo == STEV_THERMO_MLP && !m->mlp.enabled)
     return stev_fail(ctx, STEV_EINVAL, "thermo=MLP but no network attached to the mechanism");
+  if (p.hot_first != 0 && p.hot_first != 1)
+    return stev_fail(ctx, STEV_EINVAL, "hot_first must be 0 or 1");
   if (p.stab_limit != 0 && p.stab_limit != 1)
     return stev_fail(ctx, STEV_EINVAL, "stab_limit must be 0 or 1");
   if (p.stab_limit && p.thermo != STEV_THERMO_POLY)
@@ -784,7 +787,32 @@ extern "C" int stev_integrate(stev_ctx *ctx, const stev_mech *m, int64_t n_cells
   a.status_out = Sd;
   a.ctl = ctx->ctl;
   if ((rc = launch_zero(ctx, ctx->ctl, 8, s))) return rc;
+  // hottest cells first: a bucket order of the field by temperature, built on
+  // the device, read through a.cell_index by the persistent kernel
+  const bool order = p.hot_first && n_cells >= kOrderMinCells && n_cells <= INT32_MAX;
+  int *idx = nullptr;
+  unsigned long long *bins = nullptr;
+  if (order) {
+    if ((rc = ctx->sIdx.ensure(ctx, kOrderBins * sizeof(unsigned long long) +
+                                        (size_t)n_cells * sizeof(int))))
+      return rc;
+    bins = static_cast<unsigned long long *>(ctx->sIdx.ptr);
+    idx = reinterpret_cast<int *>(bins + kOrderBins);
+  }
   HIP_TRY(hipEventRecord(ctx->ev0, s));
+  if (order) {
+    if ((rc = launch_zero(ctx, bins, kOrderBins, s))) return rc;
+    const void *T_arg = Td;
+    long long n_arg = n_cells;
+    const unsigned grid = (unsigned)std::min<long long>((n_cells + 255) / 256, 1024);
+    void *cargs[] = {&T_arg, &n_arg, &bins};
+    HIP_TRY(hipLaunchKernel(kOrderCount[p.precision], dim3(grid), dim3(256), cargs, 0, s));
+    void *oargs[] = {&bins};
+    HIP_TRY(hipLaunchKernel(kOrderOffsets, dim3(1), dim3(64), oargs, 0, s));
+    void *pargs[] = {&T_arg, &n_arg, &bins, &idx};
+    HIP_TRY(hipLaunchKernel(kOrderPlace[p.precision], dim3(grid), dim3(256), pargs, 0, s));
+    a.cell_index = idx;
+  }
   if ((rc = launch_stev(ctx, lp, a, s))) return rc;
   HIP_TRY(hipEventRecord(ctx->ev1, s));
   HIP_TRY(hipMemcpyAsync(ctx->ctl_host, ctx->ctl, 8 * sizeof(unsigned long long),

@@ -28,5 +28,10 @@ extern const VariantInfo kVariants[];
 extern const void *const kMlpVariants[];   // same order; FP32 + thermo network
 extern const int kNumVariants;
 extern const void *kZeroKernel;
+// hottest-first dispatch order of a field: count, offsets, place ([precision])
+extern const void *kOrderCount[2];
+extern const void *kOrderOffsets;
+extern const void *kOrderPlace[2];
+constexpr int kOrderBins = 64;
 
 }  // namespace stev

@@ -50,7 +50,8 @@ class Params(C.Structure):
                 ("lanes_per_cell", C.c_int32), ("max_iters", C.c_int64),
                 ("waves_per_wg", C.c_int32), ("compact_every", C.c_int32),
                 ("grid_wgs", C.c_int32), ("use_graph", C.c_int32),
-                ("stab_limit", C.c_int32), ("reserved", C.c_int32)]
+                ("stab_limit", C.c_int32), ("hot_first", C.c_int32),
+                ("reserved", C.c_int32)]
 
 
 class Stats(C.Structure):

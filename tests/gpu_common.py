@@ -153,6 +153,16 @@ def judge(g, o, precision, label="", iters_equal=None):
         f"well: max_rel_T={s['max_rel_T_well']:.2e} max_rel_Y={s['max_rel_Y_well']:.2e} "
         f"iter_mismatch={s['iter_mismatch_well']} | all: max_rel_T={s['max_rel_T_all']:.2e} "
         f"max_rel_Y={s['max_rel_Y_all']:.2e}")
+    if "margin_dft" in o:
+        # decision margins: relative distance of the DFT ringing test (Eqs 10,
+        # 12) and of Y against the 1e-20 switch (Eq 2) from flipping, minimum
+        # over each cell's run; cells closer than 1e-12 are listed, not dropped
+        md, my = o["margin_dft"], o["margin_y"]
+        close = np.where((md < 1e-12) | (my < 1e-12))[0]
+        say(f"    decision margins: min DFT {md.min():.2e}, min Y-switch {my.min():.2e}; "
+            f"cells within 1e-12: {len(close)}"
+            + (f" {close[:10].tolist()} (ill-conditioned: {int(np.sum(~well[close]))})"
+               if len(close) else ""))
     bad = np.where(~ok)[0]
     for c in bad[:5]:
         say(f"    cell {c} well={well[c]} relT={relT[c]:.2e} relY={relY[c]:.2e} "

@@ -15,6 +15,10 @@ constexpr int kMaxPart = 6;    // participants per reaction (reactants + product
 constexpr int kMaxSpecies = 64;
 constexpr int kMaxReactions = 384;
 
+// Row pitches of the per-lane tables are odd numbers of values: each lane
+// reads its own row, and an odd pitch puts the lanes of a wave on distinct
+// LDS banks (a pitch of 32 values put every lane of a wave on one bank).
+//
 // --- species block: kSpStride values of R per species ------------------------
 // [SP_TMID] T_mid, [SP_W] W, [SP_INVW] 1/W, then two coefficient sets of
 // kSetLen values (low set at SP_LO, high set at SP_HI):
@@ -23,7 +27,7 @@ constexpr int kMaxReactions = 384;
 constexpr int SP_TMID = 0, SP_W = 1, SP_INVW = 2, SP_LO = 4;
 constexpr int kSetLen = 19;
 constexpr int SP_HI = SP_LO + kSetLen;
-constexpr int kSpStride = 42;
+constexpr int kSpStride = 43;
 constexpr int C_A1 = 0, C_CP = 1, C_H = 5, C_A6 = 9, C_G = 10, C_S = 14, C_A7 = 18;
 
 // --- reaction block: kRxStride values of R per reaction ------------------------
@@ -39,7 +43,7 @@ constexpr int C_A1 = 0, C_CP = 1, C_H = 5, C_A6 = 9, C_G = 10, C_S = 14, C_A7 = 
 constexpr int kHalfPart = 3;
 constexpr int RX_LNA = 0, RX_B = 1, RX_TH = 2, RX_DN = 3, RX_TMID = 4;
 constexpr int RX_ORD = 6, RX_DLO = 12, RX_DHI = 19, RX_NU = 26;
-constexpr int kRxStride = 32;
+constexpr int kRxStride = 33;
 
 // Offsets (bytes) of each array inside a mechanism blob.  Every table has one
 // extra "dummy" row (species n_s, reaction n_r) so that lanes past the end of
@@ -59,8 +63,9 @@ struct MechLayout {
   int has_frac;        // a slot carries an order other than 1 (pow needed)
   int mixed_tmid;      // some reaction's participants differ in T_mid
   int dmax;            // longest species -> reaction list
-  int dstride;         // CSR row stride: kCsrReg when dmax <= kCsrReg, else dmax
-                       // rounded up to kCsrChunk (rows padded with the zero entry)
+  int dstride;         // CSR row pitch: the padded row length (kCsrReg when
+                       // dmax <= kCsrReg, else dmax rounded up to kCsrChunk;
+                       // padding is the zero entry) plus one, so it is odd
   int bytes;           // total blob size (multiple of 16)
   int off_sp;          // R   [n_s+1][kSpStride]
   int off_rx;          // R   [n_r+1][kRxStride]
@@ -68,7 +73,8 @@ struct MechLayout {
   int off_cj;          // i32 [n_s+1][dstride]  reaction (packed order); n_r = zero entry
   int off_cnu;         // R   [n_s+1][dstride]  nu (0 on padding)
   int jwidth;          // Jacobian pattern row length (multiple of kCsrChunk)
-  int off_jp;          // i32 [n_s+1][jwidth]   Jacobian pattern (see JP_* below)
+  int jpitch;          // Jacobian pattern row pitch, jwidth + 1 (odd)
+  int off_jp;          // i32 [n_s+1][jpitch]   Jacobian pattern (see JP_* below)
 };
 
 // Jacobian pattern entry of species row i (Eq 25 limiter): the derivative

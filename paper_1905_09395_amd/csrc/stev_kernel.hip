@@ -726,7 +726,7 @@ stev_persistent(const KArgs a) {
     if constexpr (STAB) {
 #pragma unroll
       for (int s = 0; s < SPL; ++s) {
-        const unsigned *je = jpt + kk[s] * a.L.jwidth;
+        const unsigned *je = jpt + kk[s] * a.L.jpitch;
         R row = R(0), acc = R(0);
         for (int e0 = 0; e0 < a.L.jwidth; e0 += kCsrChunk) {
           unsigned ev[kCsrChunk];

@@ -226,8 +226,8 @@ static void pack_blob(const stev_mech *m, std::vector<unsigned char> &blob, Mech
   L.mixed_tmid = m->mixed_tmid;
   L.dmax = m->dmax;
   // rows padded (zero-rate entry, nu = 0) to the register walk's length, or
-  // to a multiple of the generic walk's chunk
-  L.dstride = m->dmax <= kCsrReg ? kCsrReg : (m->dmax + kCsrChunk - 1) / kCsrChunk * kCsrChunk;
+  // to a multiple of the generic walk's chunk, plus one entry for an odd pitch
+  L.dstride = (m->dmax <= kCsrReg ? kCsrReg : (m->dmax + kCsrChunk - 1) / kCsrChunk * kCsrChunk) + 1;
   L.nnz_csr = (n_s + 1) * L.dstride;
   int off = 0;
   L.off_sp = off;   off = align16(off + (n_s + 1) * kSpStride * (int)sizeof(R));
@@ -236,7 +236,8 @@ static void pack_blob(const stev_mech *m, std::vector<unsigned char> &blob, Mech
   L.off_cj = off;   off = align16(off + L.nnz_csr * 4);
   L.off_cnu = off;  off = align16(off + L.nnz_csr * (int)sizeof(R));
   L.jwidth = m->jwidth;
-  L.off_jp = off;   off = align16(off + (n_s + 1) * m->jwidth * 4);
+  L.jpitch = m->jwidth + 1;
+  L.off_jp = off;   off = align16(off + (n_s + 1) * L.jpitch * 4);
   L.bytes = std::max(off, 16);
   blob.assign(L.bytes, 0);
   R *sp = reinterpret_cast<R *>(blob.data() + L.off_sp);
@@ -303,7 +304,11 @@ static void pack_blob(const stev_mech *m, std::vector<unsigned char> &blob, Mech
       cnu[k * L.dstride + e] = used ? (R)m->csr_nu[m->csr_ptr[k] + e] : (R)0;
     }
   }
-  std::memcpy(blob.data() + L.off_jp, m->jp.data(), m->jp.size() * 4);
+  unsigned *jp = reinterpret_cast<unsigned *>(blob.data() + L.off_jp);
+  for (int k = 0; k <= n_s; ++k) {
+    std::memcpy(jp + (size_t)k * L.jpitch, m->jp.data() + (size_t)k * L.jwidth, L.jwidth * 4);
+    jp[(size_t)k * L.jpitch + L.jwidth] = m->jp[(size_t)k * L.jwidth];   // pad: never read
+  }
 }
 
 // Jacobian pattern (Eq 25 limiter): for species i, every (reaction, rate-law

@@ -91,45 +91,69 @@ __device__ __forceinline__ double xchg(double v) {
   return __hiloint2double(hi, lo);
 }
 
-template <int G, typename V>
-__device__ __forceinline__ V grp_sum(V v) {
-  if constexpr (G >= 2) v += xchg<1>(v);
-  if constexpr (G >= 4) v += xchg<2>(v);
-  if constexpr (G >= 8) v += xchg<4>(v);
-  if constexpr (G >= 16) v += xchg<8>(v);
-  if constexpr (G >= 32) v += xchg<16>(v);
-  if constexpr (G >= 64) v += xchg<32>(v);
+// A permlane swap of a value with itself returns {own, partner} in some
+// order in every lane; a commutative combine of the pair needs no select.
+template <int STEP>
+__device__ __forceinline__ void swap_pair(int v, int &a, int &b) {
+  if constexpr (STEP == 16) {
+    auto p = __builtin_amdgcn_permlane16_swap((unsigned)v, (unsigned)v, false, false);
+    a = (int)p[0];
+    b = (int)p[1];
+  } else {
+    auto p = __builtin_amdgcn_permlane32_swap((unsigned)v, (unsigned)v, false, false);
+    a = (int)p[0];
+    b = (int)p[1];
+  }
+}
+template <int STEP>
+__device__ __forceinline__ void swap_pair(double v, double &a, double &b) {
+  int al, bl, ah, bh;
+  swap_pair<STEP>(__double2loint(v), al, bl);
+  swap_pair<STEP>(__double2hiint(v), ah, bh);
+  a = __hiloint2double(ah, al);
+  b = __hiloint2double(bh, bl);
+}
+template <int STEP>
+__device__ __forceinline__ void swap_pair(float v, float &a, float &b) {
+  int ai, bi;
+  swap_pair<STEP>(__float_as_int(v), ai, bi);
+  a = __int_as_float(ai);
+  b = __int_as_float(bi);
+}
+struct OpSum { template <typename V> __device__ static V f(V x, V y) { return x + y; } };
+struct OpMin { template <typename V> __device__ static V f(V x, V y) { return fmin(x, y); } };
+struct OpMax { template <typename V> __device__ static V f(V x, V y) { return fmax(x, y); } };
+
+template <int G, typename Op, typename V>
+__device__ __forceinline__ V grp_reduce(V v) {
+  if constexpr (G >= 2) v = Op::f(v, xchg<1>(v));
+  if constexpr (G >= 4) v = Op::f(v, xchg<2>(v));
+  if constexpr (G >= 8) v = Op::f(v, xchg<4>(v));
+  if constexpr (G >= 16) v = Op::f(v, xchg<8>(v));
+  if constexpr (G == 64) {
+    V a, b;
+    swap_pair<16>(v, a, b);
+    v = Op::f(a, b);
+    swap_pair<32>(v, a, b);
+    v = Op::f(a, b);
+  } else if constexpr (G == 32) {   // the select form keeps this variant's registers down
+    v = Op::f(v, xchg<16>(v));
+  }
   return v;
 }
-template <int G, typename V>
-__device__ __forceinline__ V grp_min(V v) {
-  if constexpr (G >= 2) v = fmin(v, xchg<1>(v));
-  if constexpr (G >= 4) v = fmin(v, xchg<2>(v));
-  if constexpr (G >= 8) v = fmin(v, xchg<4>(v));
-  if constexpr (G >= 16) v = fmin(v, xchg<8>(v));
-  if constexpr (G >= 32) v = fmin(v, xchg<16>(v));
-  if constexpr (G >= 64) v = fmin(v, xchg<32>(v));
-  return v;
-}
-template <int G, typename V>
-__device__ __forceinline__ V grp_max(V v) {
-  if constexpr (G >= 2) v = fmax(v, xchg<1>(v));
-  if constexpr (G >= 4) v = fmax(v, xchg<2>(v));
-  if constexpr (G >= 8) v = fmax(v, xchg<4>(v));
-  if constexpr (G >= 16) v = fmax(v, xchg<8>(v));
-  if constexpr (G >= 32) v = fmax(v, xchg<16>(v));
-  if constexpr (G >= 64) v = fmax(v, xchg<32>(v));
-  return v;
-}
+template <int G, typename V> __device__ __forceinline__ V grp_sum(V v) { return grp_reduce<G, OpSum>(v); }
+template <int G, typename V> __device__ __forceinline__ V grp_min(V v) { return grp_reduce<G, OpMin>(v); }
+template <int G, typename V> __device__ __forceinline__ V grp_max(V v) { return grp_reduce<G, OpMax>(v); }
+// any lane of the group set: one ballot
 template <int G>
 __device__ __forceinline__ int grp_or(int v) {
-  if constexpr (G >= 2) v |= xchg<1>(v);
-  if constexpr (G >= 4) v |= xchg<2>(v);
-  if constexpr (G >= 8) v |= xchg<4>(v);
-  if constexpr (G >= 16) v |= xchg<8>(v);
-  if constexpr (G >= 32) v |= xchg<16>(v);
-  if constexpr (G >= 64) v |= xchg<32>(v);
-  return v;
+  const unsigned long long m = __ballot(v != 0);
+  if constexpr (G == 64) {
+    return m != 0ull;
+  } else {
+    const int gi = (threadIdx.x & 63) / G;
+    return ((m >> (gi * G)) & ((1ull << G) - 1ull)) != 0ull;
+  }
 }
 
 template <typename R> struct Math;
@@ -783,7 +807,11 @@ stev_persistent(const KArgs a) {
       R x[RRPL];
 #pragma unroll
       for (int r = 0; r < RRPL; ++r) x[r] = q[r] * hR;
-      if constexpr (G == 64) {   // one cell per wave: the slot is wave-uniform
+      if constexpr (G == 64 && RRPL == 1) {
+        // one cell per wave and one ring per lane: a wave-uniform index into
+        // the register array, one indirect move per half, no copies
+        if (commit) ring[0][__builtin_amdgcn_readfirstlane(rs)] = x[0];
+      } else if constexpr (G == 64) {   // the slot is wave-uniform
         if (commit) {
           switch (__builtin_amdgcn_readfirstlane(rs)) {
 #define STEV_RING_WRITE(M) \

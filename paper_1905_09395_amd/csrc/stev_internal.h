@@ -152,6 +152,11 @@ struct KArgs {
   // single batch only: the launch's i-th cell is cell cell_index[i] of the
   // arrays (nullptr: cell i); the dispatch order of a field
   const int *cell_index;
+  // with a dispatch order, workgroups below n_front take cells from its
+  // front (hottest first) and the others from its back: ctl[0] then packs
+  // the two claim counts (front in the low, back in the high 32 bits).
+  // 0: one counter, front only
+  int n_front;
   MlpDev mlp;
 };
 

@@ -443,14 +443,35 @@ stev_persistent(const KArgs a) {
       const unsigned long long m = __ballot(want && l == 0);
       if (m) {
         const int nwant = __popcll(m);
+        // two-ended claims: a claim from one end is valid while it has not
+        // reached what the other end had claimed when it was made, so each
+        // cell is taken exactly once and both ends run dry together
+        const bool back = a.n_front > 0 && (int)blockIdx.x >= a.n_front;
         unsigned long long base = 0;
-        if (lane == 0) base = atomicAdd(&a.ctl[0], (unsigned long long)nwant);
+        if (lane == 0)
+          base = atomicAdd(&a.ctl[0], back ? ((unsigned long long)nwant << 32)
+                                           : (unsigned long long)nwant);
         base = __shfl(base, 0);
         const unsigned long long below = (gi == 0) ? 0ull : (m & ((1ull << (gi * G)) - 1ull));
         const int rank = __popcll(below);
         if (want) {
-          const long long g = (long long)base + rank;
-          if (g < a.n_cells) {
+          long long g;
+          bool ok;
+          if (a.n_front == 0) {
+            g = (long long)base + rank;
+            ok = g < a.n_cells;
+          } else {
+            const long long f = (long long)(base & 0xffffffffull), b = (long long)(base >> 32);
+            if (back) {
+              const long long pos = b + rank;
+              g = a.n_cells - 1 - pos;
+              ok = pos < a.n_cells - f;
+            } else {
+              g = f + rank;
+              ok = g < a.n_cells - b;
+            }
+          }
+          if (ok) {
             cb = a.batches ? find_batch(a, g) : -1;
             cell = a.batches ? g - a.batches[cb].begin : (a.cell_index ? a.cell_index[g] : g);
             const CellRef<R> cr = cell_ref<R>(a, cb, cell);

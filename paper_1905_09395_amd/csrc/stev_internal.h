@@ -58,6 +58,14 @@ constexpr int kCsrReg = 24;
 constexpr int kCsrChunk = 8;
 static_assert(kCsrReg % kCsrChunk == 0, "register rows must also pad to whole chunks");
 
+// FP64 exp / log tables, at offset 0 of a double-precision blob (so at LDS
+// offset 0 once staged): 2^(j/64) as hi, lo for j < kExpTab, then for
+// j < kLogTab the triple ic, -log(ic) hi, lo with ic = 1/(1 + (j + 1/2)/kLogTab)
+// rounded to double.
+constexpr int kExpTab = 64;
+constexpr int kLogTab = 32;
+constexpr int kXtabBytes = (2 * kExpTab + 3 * kLogTab) * 8;
+
 struct MechLayout {
   int n_s, n_r, n_rev, nnz_csr;
   int has_frac;        // a slot carries an order other than 1 (pow needed)
@@ -67,6 +75,7 @@ struct MechLayout {
                        // dmax <= kCsrReg, else dmax rounded up to kCsrChunk;
                        // padding is the zero entry) plus one, so it is odd
   int bytes;           // total blob size (multiple of 16)
+  int off_xtab;        // FP64 exp / log tables (double blobs only; else -1)
   int off_sp;          // R   [n_s+1][kSpStride]
   int off_rx;          // R   [n_r+1][kRxStride]
   int off_rxi;         // i32 [n_r+1][kMaxPart] slot species: n_s = unit entry

@@ -156,10 +156,61 @@ __device__ __forceinline__ int grp_or(int v) {
   }
 }
 
+// Dynamic LDS of the persistent kernel; a double-precision mechanism blob
+// is staged at its start, FP64 exp / log tables first.
+extern __shared__ __align__(16) unsigned char stev_lds[];
+
+// exp in FP64: x = (64 k + j) ln2/64 + r with |r| <= ln2/128 (Cody-Waite
+// split of ln2/64, the high part exact for any product with n), so
+// e^x = 2^k 2^(j/64) (1 + p(r)), 2^(j/64) from the table as hi + lo and
+// p(r) = e^r - 1 from its Taylor series through r^6 (truncation < 2^-58).
+// Arguments are clamped to [-1e4, 1e4], which leaves 0 and inf where they
+// belong; a NaN argument comes out as 0 (every NaN input to the kernel also
+// reaches the state through other terms and fails the cell there).
+constexpr double kExpInvL = 0x1.71547652b82fep+6;   // 64 / ln 2
+constexpr double kLn2Hi = 0x1.62e42p-1;             // ln 2, 20 significant bits
+constexpr double kLn2Lo = 0x1.fdf473de6af28p-22;    // ln 2 - kLn2Hi
+__device__ __forceinline__ double exp_tab(double x) {
+  const double *t = reinterpret_cast<const double *>(stev_lds);
+  x = fmin(fmax(x, -1.0e4), 1.0e4);
+  const double n = rint(x * kExpInvL);
+  const int ni = (int)n;
+  const double r = fma(-n, kLn2Lo / kExpTab, fma(-n, kLn2Hi / kExpTab, x));
+  double p = fma(r, 1.0 / 720.0, 1.0 / 120.0);
+  p = fma(r, p, 1.0 / 24.0);
+  p = fma(r, p, 1.0 / 6.0);
+  p = fma(r, p, 0.5);
+  p = fma(r * r, p, r);
+  const int j = ni & (kExpTab - 1);
+  const double th = t[2 * j], tl = t[2 * j + 1];
+  return ldexp(fma(th, p, tl) + th, ni >> 6);
+}
+// log in FP64: x = 2^e m with m in [1, 2) and j the top five fraction bits
+// of m; with ic from the table, r = m ic - 1 carries a single rounding and
+// |r| < 1/64, and log x = e ln2 - log(ic) + log1p(r), log1p from its series
+// through r^8 (truncation < 2^-56).  x <= 0 and NaN go to the library log.
+__device__ __forceinline__ double log_tab(double x) {
+  const double *t = reinterpret_cast<const double *>(stev_lds) + 2 * kExpTab;
+  int e;
+  const double m = 2.0 * frexp(x, &e);
+  const int j = (__double2hiint(m) >> 15) & (kLogTab - 1);
+  const double ic = t[3 * j], lh = t[3 * j + 1], ll = t[3 * j + 2];
+  const double r = fma(m, ic, -1.0);
+  double q = fma(r, -1.0 / 8.0, 1.0 / 7.0);
+  q = fma(r, q, -1.0 / 6.0);
+  q = fma(r, q, 1.0 / 5.0);
+  q = fma(r, q, -0.25);
+  q = fma(r, q, 1.0 / 3.0);
+  q = fma(r, q, -0.5);
+  const double de = (double)(e - 1);
+  const double res = fma(de, kLn2Hi, lh) + (fma(r * r, q, r) + fma(de, kLn2Lo, ll));
+  return x > 0.0 ? res : log(x);
+}
+
 template <typename R> struct Math;
 template <> struct Math<double> {
-  static __device__ __forceinline__ double ex(double x) { return exp(x); }
-  static __device__ __forceinline__ double lg(double x) { return log(x); }
+  static __device__ __forceinline__ double ex(double x) { return exp_tab(x); }
+  static __device__ __forceinline__ double lg(double x) { return log_tab(x); }
   static __device__ __forceinline__ bool fin(double x) { return isfinite(x); }
 };
 template <> struct Math<float> {
@@ -264,7 +315,7 @@ __device__ __forceinline__ void stab_slot_derivs(const R (&C)[kMaxPart], R kf, R
 template <typename R, int G, int RPL, int RRPL, int SPL, int CSRR, bool MLP, bool STAB>
 __global__ void __launch_bounds__(256)
 stev_persistent(const KArgs a) {
-  extern __shared__ __align__(16) unsigned char smem[];
+  unsigned char *const smem = stev_lds;
   constexpr int CPW = 64 / G;
   constexpr int NT = (CPW + 15) / 16;   // 16-cell MFMA column tiles per wave
 
@@ -860,19 +911,12 @@ stev_persistent(const KArgs a) {
     }
   }
 
-  // flush statistics: one atomic per wave and counter
-  long long s_it = sum_it, m_it = max_it, n_f = n_fail;
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    s_it += __shfl_xor(s_it, off);
-    n_f += __shfl_xor(n_f, off);
-    const long long o = __shfl_xor(m_it, off);
-    m_it = o > m_it ? o : m_it;
-  }
-  if (lane == 0) {
-    if (s_it) atomicAdd(&a.ctl[1], (unsigned long long)s_it);
-    if (m_it) atomicMax(&a.ctl[2], (unsigned long long)m_it);
-    if (n_f) atomicAdd(&a.ctl[3], (unsigned long long)n_f);
+  // flush statistics: each group leader adds its counts (the compiler
+  // combines the atomics of a wavefront into one per counter)
+  if (l == 0) {
+    if (sum_it) atomicAdd(&a.ctl[1], (unsigned long long)sum_it);
+    if (max_it) atomicMax(&a.ctl[2], (unsigned long long)max_it);
+    if (n_fail) atomicAdd(&a.ctl[3], (unsigned long long)n_fail);
   }
 }
 

@@ -207,6 +207,24 @@ __device__ __forceinline__ double log_tab(double x) {
   return x > 0.0 ? res : log(x);
 }
 
+// a / b from the hardware reciprocal: Newton steps on 1/b, then one
+// correction of the quotient by its exact remainder (an FMA).  The result
+// is within an ulp of the IEEE quotient and equal to it in nearly every
+// case; a zero, infinite or NaN divisor gives a non-finite result.
+__device__ __forceinline__ double qdiv(double a, double b) {
+  double r = __builtin_amdgcn_rcp(b);
+  r = fma(fma(-b, r, 1.0), r, r);
+  r = fma(fma(-b, r, 1.0), r, r);
+  const double q = a * r;
+  return fma(fma(-b, q, a), r, q);
+}
+__device__ __forceinline__ float qdiv(float a, float b) {
+  float r = __builtin_amdgcn_rcpf(b);
+  r = fmaf(fmaf(-b, r, 1.0f), r, r);
+  const float q = a * r;
+  return fmaf(fmaf(-b, q, a), r, q);
+}
+
 template <typename R> struct Math;
 template <> struct Math<double> {
   static __device__ __forceinline__ double ex(double x) { return exp_tab(x); }
@@ -554,7 +572,7 @@ stev_persistent(const KArgs a) {
 
     // ---- one STEV iteration ---------------------------------------------------
     const R lnT = Math<R>::lg(T);
-    const R invT = R(1) / T;
+    const R invT = qdiv(R(1), T);
     const R lnPRT = ln_patm_r - lnT;
     const R omlnT = R(1) - lnT;
 
@@ -657,12 +675,12 @@ stev_persistent(const KArgs a) {
     sumYW = grp_sum<G>(sumYW);
     sumYcp = grp_sum<G>(sumYcp);
     const R RTs = rgas * T * sumYW;
-    const R rho = P / RTs;             // P Wbar / (R T)
+    const R rho = qdiv(P, RTs);        // P Wbar / (R T)
     const R inv_rho = RTs * invP;
 #pragma unroll
     for (int s = 0; s < SPL; ++s) {
       const R yp = Y[s] > R(0) ? Y[s] : R(0);
-      const R yss = yp * yp / (alpha + yp);                          // Eqs 6-7
+      const R yss = qdiv(yp * yp, alpha + yp);                       // Eqs 6-7
       sC[crow[s]] = (yp > R(0)) ? rho * yss * invW[s] : R(0);
       if constexpr (STAB) {
         // dC/dY = (rho / W) Y (Y + 2 alpha) / (alpha + Y)^2; for slots of
@@ -813,7 +831,7 @@ stev_persistent(const KArgs a) {
       sum_hw += hRT[s] * om;
       const R rstar = fmax(-rk, R(1e-30));                       // Eq 1
       const R ystar = (Y[s] < R(1e-20)) ? R(1) : R(0.9) * Y[s];  // Eq 2
-      tst = fmin(tst, fmin(ystep, ystar) / rstar);               // Eq 3
+      tst = fmin(tst, qdiv(fmin(ystep, ystar), rstar));          // Eq 3
     }
     // Eq 25: ||A||_inf of A = d(dY/dt)/dY at fixed T and rho.  Row i walks
     // its pattern: per column, the sum of nu_i,jn * d(q_eff,jn)/dY_j over the
@@ -846,7 +864,7 @@ stev_persistent(const KArgs a) {
     }
     sum_hw = grp_sum<G>(sum_hw);
     tst = grp_min<G>(tst);
-    const R dTdt = -T * sum_hw * inv_rho / sumYcp;
+    const R dTdt = qdiv(-T * sum_hw * inv_rho, sumYcp);
     double h = fmin((double)tst, dtmax);   // Eqs 4-5
     h = fmin(h, tf - t);
     if constexpr (STAB) {

@@ -214,6 +214,58 @@ typedef struct {
 int stev_train_thermo_mlp(stev_ctx *ctx, stev_mech *mech, const stev_mlp_cfg *cfg,
                           stev_mlp_report *report);
 
+/* The paper's own thermo network and trainer (Sec 3): one sigmoid hidden
+ * layer, as wide as the outputs by default, and a linear output layer,
+ * fitted by Levenberg-Marquardt.  Parameters are FP64, laid out as
+ * [W2 (n_out x H, row-major), b2 (n_out), w1 (H), b1 (H)] for
+ * y = W2 sigmoid(w1 x + b1) + b2.  Each step solves
+ * (J^T J + lambda D) d = -J^T r with D = diag(J^T J) + 1e-6 mean(diag(J^T J))
+ * (Marquardt's diagonal with a floor); the sums forming J^T J and J^T r
+ * run on the GPU, and the solve eliminates the output-layer blocks (all the
+ * same matrix) before a 2H x 2H system for the hidden layer.  H and n_out
+ * are at most 64 (6- and 19-species mechanisms). */
+typedef struct {
+  int32_t hidden;        /* hidden units; 0: as many as outputs (2 n_s) */
+  int32_t iters;         /* Levenberg-Marquardt iterations (accepted or not) */
+  int64_t n_samples;     /* temperatures uniform in [T_lo, T_hi]; >= 256 */
+  double T_lo, T_hi;
+  double holdout_frac;   /* the last fraction is held out, in (0, 0.5) */
+  double lambda0;        /* initial damping, > 0; /10 after an accepted
+                            step, x10 after a rejected one */
+  uint64_t seed;
+} stev_lma_cfg;
+
+typedef struct {
+  int32_t hidden;
+  int32_t accepted, rejected;
+  int32_t reserved;
+  int64_t n_params;
+  double train_loss, test_loss;     /* mean squared z-scored residual */
+  double max_rel_cp, mean_rel_cp;   /* cp/R against the polynomials, held out */
+  double final_lambda;
+  double train_ms;
+} stev_lma_report;
+
+/* Parameters of a network with `hidden` units and `n_out` outputs. */
+int64_t stev_lma_n_params(int32_t hidden, int32_t n_out);
+
+/* Train on the mechanism's FP64 polynomials (targets z-scored per output,
+ * x = (T - 1650) / 1350).  params_out (nullable, host, stev_lma_n_params
+ * doubles) receives the trained parameters.  The mechanism is not changed.
+ * STEV_EINVAL on a bad configuration or shape, STEV_ENOMEM if the buffers
+ * do not fit the HBM budget. */
+int stev_train_thermo_lma(stev_ctx *ctx, const stev_mech *mech, const stev_lma_cfg *cfg,
+                          stev_lma_report *report, double *params_out);
+
+/* One evaluation of the normal equations on the GPU for given parameters
+ * and samples (host arrays: params, x[n], target[n * n_out] row-major).
+ * Outputs, each nullable: jtj (P x P row-major), jtr (P), loss (sum of
+ * squared residuals), and step, the Levenberg-Marquardt step for `lambda`.
+ * STEV_EINVAL also when the damped system is not positive definite. */
+int stev_lma_normal_eq(stev_ctx *ctx, int32_t hidden, int32_t n_out, const double *params,
+                       int64_t n, const double *x, const double *target, double lambda,
+                       double *jtj, double *jtr, double *loss, double *step);
+
 /* Export / import the FP32 master weights of an attached network
  * (layout W1[H] b1[H] W2[H][H] b2[H] W3[2n][H] b3[2n], then 4n z-score
  * constants mean_cp[n] std_cp[n] mean_h[n] std_h[n]).  n_values in/out. */

@@ -83,6 +83,23 @@ class MlpReport(C.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class LmaCfg(C.Structure):
+    _fields_ = [("hidden", C.c_int32), ("iters", C.c_int32), ("n_samples", C.c_int64),
+                ("T_lo", C.c_double), ("T_hi", C.c_double), ("holdout_frac", C.c_double),
+                ("lambda0", C.c_double), ("seed", C.c_uint64)]
+
+
+class LmaReport(C.Structure):
+    _fields_ = [("hidden", C.c_int32), ("accepted", C.c_int32), ("rejected", C.c_int32),
+                ("reserved", C.c_int32), ("n_params", C.c_int64),
+                ("train_loss", C.c_double), ("test_loss", C.c_double),
+                ("max_rel_cp", C.c_double), ("mean_rel_cp", C.c_double),
+                ("final_lambda", C.c_double), ("train_ms", C.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 _lib = None
 
 
@@ -121,6 +138,11 @@ def load():
     L.stev_autotune.argtypes = [vp, vp, i64, vp, vp, vp, i64, i64, dbl, C.POINTER(Params)]
     L.stev_mlp_loss_grad.argtypes = [vp, i32, i32, vp, i64, vp, vp, vp, C.POINTER(dbl)]
     L.stev_thermo_eval.argtypes = [vp, vp, i32, i64, vp, vp, vp]
+    L.stev_lma_n_params.argtypes = [i32, i32]
+    L.stev_lma_n_params.restype = i64
+    L.stev_train_thermo_lma.argtypes = [vp, vp, C.POINTER(LmaCfg), C.POINTER(LmaReport), vp]
+    L.stev_lma_normal_eq.argtypes = [vp, i32, i32, vp, i64, vp, vp, dbl, vp, vp,
+                                     C.POINTER(dbl), vp]
     L.stev_model_flops.argtypes = [vp, i32, C.POINTER(dbl)]
     L.stev_model_flops.restype = dbl
     L.stev_destroy_mechanism.argtypes = [vp, vp]
@@ -334,6 +356,38 @@ class Context:
         v = np.ascontiguousarray(values, dtype=np.float32)
         self._check(self.lib.stev_set_thermo_mlp(self.h, mech.h, int(hidden), float(T_lo),
                                                  float(T_hi), v.ctypes.data, len(v)))
+
+    def train_thermo_lma(self, mech, **cfg):
+        """The paper's sigmoid network fitted by Levenberg-Marquardt on the
+        GPU; returns (report dict, FP64 parameters)."""
+        c = LmaCfg(0, 60, 1 << 16, 300.0, 3000.0, 0.125, 1e-2, 104)
+        for k, v in cfg.items():
+            setattr(c, k, v)
+        rep = LmaReport()
+        n_out = 2 * mech.n_s
+        H = c.hidden if c.hidden > 0 else n_out
+        prm = np.zeros(self.lib.stev_lma_n_params(H, n_out))
+        self._check(self.lib.stev_train_thermo_lma(self.h, mech.h, C.byref(c), C.byref(rep),
+                                                   prm.ctypes.data))
+        return rep.as_dict(), prm
+
+    def lma_normal_eq(self, hidden, n_out, params, x, target, lam=None, jtj=True):
+        """GPU normal equations (J^T J, J^T r, loss) and, with lam, the
+        Levenberg-Marquardt step; host FP64 arrays."""
+        p = np.ascontiguousarray(params, dtype=np.float64)
+        xx = np.ascontiguousarray(x, dtype=np.float64)
+        t = np.ascontiguousarray(target, dtype=np.float64)
+        P = len(p)
+        A = np.zeros((P, P)) if jtj else None
+        g = np.zeros(P)
+        d = np.zeros(P) if lam is not None else None
+        loss = C.c_double()
+        self._check(self.lib.stev_lma_normal_eq(
+            self.h, int(hidden), int(n_out), p.ctypes.data, len(xx), xx.ctypes.data,
+            t.ctypes.data, float(lam if lam is not None else 0.0),
+            A.ctypes.data if A is not None else None, g.ctypes.data, C.byref(loss),
+            d.ctypes.data if d is not None else None))
+        return A, g, loss.value, d
 
     def mlp_loss_grad(self, n_out, params, x, target, hidden=32):
         """GPU loss and gradient of a thermo network (FP32), host arrays."""

@@ -43,9 +43,10 @@ def test_struct_sizes_match_header():
 #include <stddef.h>
 #include "stev.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu %zu\n", sizeof(stev_params), sizeof(stev_stats),
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(stev_params), sizeof(stev_stats),
          sizeof(stev_mech_desc), sizeof(stev_mlp_cfg), sizeof(stev_mlp_report),
-         offsetof(stev_params, max_iters));
+         offsetof(stev_params, max_iters), sizeof(stev_lma_cfg), sizeof(stev_lma_report),
+         offsetof(stev_lma_report, train_loss));
   return 0;
 }
 '''
@@ -58,4 +59,5 @@ int main(void) {
     sizes = [int(x) for x in out]
     assert sizes == [C.sizeof(stev.Params), C.sizeof(stev.Stats), C.sizeof(stev.MechDesc),
                      C.sizeof(stev.MlpCfg), C.sizeof(stev.MlpReport),
-                     stev.Params.max_iters.offset]
+                     stev.Params.max_iters.offset, C.sizeof(stev.LmaCfg),
+                     C.sizeof(stev.LmaReport), stev.LmaReport.train_loss.offset]

@@ -188,7 +188,12 @@ __device__ __forceinline__ double exp_tab(double x) {
 // log in FP64: x = 2^e m with m in [1, 2) and j the top five fraction bits
 // of m; with ic from the table, r = m ic - 1 carries a single rounding and
 // |r| < 1/64, and log x = e ln2 - log(ic) + log1p(r), log1p from its series
-// through r^8 (truncation < 2^-56).  x <= 0 and NaN go to the library log.
+// through r^8 (truncation < 2^-56).  The special arguments are selected,
+// not branched to: 0 gives -inf, +inf gives +inf, negatives and NaN give NaN.
+// A branch here opens a region that runs with part of the wavefront masked
+// off, and the register allocator has been seen to place copies of values
+// that live across the whole loop (the per-lane statistics) inside such a
+// region, so lanes holding a bad temperature lost them.
 __device__ __forceinline__ double log_tab(double x) {
   const double *t = reinterpret_cast<const double *>(stev_lds) + 2 * kExpTab;
   int e;
@@ -204,7 +209,8 @@ __device__ __forceinline__ double log_tab(double x) {
   q = fma(r, q, -0.5);
   const double de = (double)(e - 1);
   const double res = fma(de, kLn2Hi, lh) + (fma(r * r, q, r) + fma(de, kLn2Lo, ll));
-  return x > 0.0 ? res : log(x);
+  const double sp = (x == 0.0) ? -__builtin_inf() : ((x > 0.0) ? x : __builtin_nan(""));
+  return (x > 0.0 && x < __builtin_inf()) ? res : sp;
 }
 
 // a / b from the hardware reciprocal: Newton steps on 1/b, then one
@@ -441,6 +447,14 @@ stev_persistent(const KArgs a) {
       coff[s][e] = csr_reg ? (o0 | (o1 << 16)) : 0u;
     }
 
+  // range-switch temperatures of the lane's species and reactions, held in
+  // registers so that the choice of coefficient set needs no LDS round trip
+  R tmid_s[SPL], tmid_r[RPL];
+#pragma unroll
+  for (int s = 0; s < SPL; ++s) tmid_s[s] = spT[kk[s] * kSpStride + SP_TMID];
+#pragma unroll
+  for (int r = 0; r < RPL; ++r) tmid_r[r] = rxR[jj[r] * kRxStride + RX_TMID];
+
   const R ystep = R(a.ystep), alpha = R(a.alpha);
   const R tol_ring2 = R(a.tol_ring2), tol_freq = R(a.tol_freq);
   const R r_fac = R(a.r_fac), r_fac_inv = R(a.r_fac_inv), rof_min = R(a.rof_min);
@@ -620,7 +634,7 @@ stev_persistent(const KArgs a) {
         kf_e[r] = Math<R>::ex(lnkf);
         ek_e[r] = R(0);
         if (n_rev > 0 && !mixed) {
-          const R *d = rr + ((T < rr[RX_TMID]) ? RX_DLO : RX_DHI);
+          const R *d = rr + ((T < tmid_r[r < RPL ? r : 0]) ? RX_DLO : RX_DHI);
           const R dG = d[0] * omlnT + T * (d[1] + T * (d[2] + T * (d[3] + T * d[4]))) + d[5] * invT - d[6];
           const R lnKc = rr[RX_DN] * lnPRT - dG;
           ek_e[r] = Math<R>::ex(-lnKc);
@@ -650,7 +664,7 @@ stev_persistent(const KArgs a) {
       const R *sp = spT + kk[s] * kSpStride;
       invW[s] = sp[SP_INVW];
       Wk[s] = sp[SP_W];
-      const R *c = sp + ((T < sp[SP_TMID]) ? SP_LO : SP_HI);
+      const R *c = sp + ((T < tmid_s[s]) ? SP_LO : SP_HI);
       const R a1 = c[C_A1], a6 = c[C_A6];
       if (need_poly) {
         cpR[s] = a1 + T * (c[C_CP] + T * (c[C_CP + 1] + T * (c[C_CP + 2] + T * c[C_CP + 3])));
@@ -715,7 +729,7 @@ stev_persistent(const KArgs a) {
         } else {
           const R lnkf = rr[RX_LNA] + rr[RX_B] * lnT - rr[RX_TH] * invT;
           kf = Math<R>::ex(lnkf);
-          const R *d = rr + ((T < rr[RX_TMID]) ? RX_DLO : RX_DHI);
+          const R *d = rr + ((T < tmid_r[r < RPL ? r : 0]) ? RX_DLO : RX_DHI);
           const R dG = d[0] * omlnT + T * (d[1] + T * (d[2] + T * (d[3] + T * d[4]))) + d[5] * invT - d[6];
           const R lnKc = rr[RX_DN] * lnPRT - dG;
           ek = Math<R>::ex(-lnKc);
@@ -765,7 +779,7 @@ stev_persistent(const KArgs a) {
         } else {
           R dG;
           if (!mixed) {
-            const R *d = rr + ((T < rr[RX_TMID]) ? RX_DLO : RX_DHI);
+            const R *d = rr + ((T < tmid_r[r < RPL ? r : 0]) ? RX_DLO : RX_DHI);
             dG = d[0] * omlnT + T * (d[1] + T * (d[2] + T * (d[3] + T * d[4]))) + d[5] * invT - d[6];
           } else {
             dG = R(0);

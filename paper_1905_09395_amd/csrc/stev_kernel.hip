@@ -435,17 +435,32 @@ stev_persistent(const KArgs a) {
   // species -> reaction CSR offsets held in registers (two 16-bit offsets per
   // VGPR) when the padded width fits; otherwise read from LDS each iteration
   const bool csr_reg = (CSRR > 0) && (dmax <= CSRR);
+  // With one cell per wave and at most 32 species, lanes l and l + 32 share
+  // species l's row, each walking half of the padded row (kHalf entries from
+  // `half * kHalf`), and the two partial sums are added across the halves of
+  // the wavefront: half the LDS gathers and half the dependent FMA chain.
+  constexpr bool kSplitRow = (G == 64) && (SPL == 1) && (CSRR > 0);
+  constexpr int kHalf = CSRR / 2;
+  const bool split = kSplitRow && csr_reg && n_s <= 32;
+  const int half = (split && l >= 32) ? 1 : 0;
+  const int srow = split ? (((l & 31) < n_s) ? (l & 31) : n_s) : kk[0];
   unsigned coff[SPL][(CSRR + 1) / 2];
 #pragma unroll
   for (int s = 0; s < SPL; ++s)
 #pragma unroll
     for (int e = 0; e < (CSRR + 1) / 2; ++e) {
-      const int e0 = 2 * e, e1 = 2 * e + 1;
+      int e0 = 2 * e, e1 = 2 * e + 1;
+      if (split) {   // registers past the half row keep in-row entries, unused
+        e0 = e0 < kHalf ? half * kHalf + e0 : e0;
+        e1 = e1 < kHalf ? half * kHalf + e1 : e1;
+      }
+      const int row = split ? srow : kk[s];
       // rows are padded to kCsrReg with the zero-rate entry n_r
-      const unsigned o0 = (unsigned)(cj[kk[s] * dstride + e0] * CPW + gi);
-      const unsigned o1 = (unsigned)(cj[kk[s] * dstride + e1] * CPW + gi);
+      const unsigned o0 = (unsigned)(cj[row * dstride + e0] * CPW + gi);
+      const unsigned o1 = (unsigned)(cj[row * dstride + e1] * CPW + gi);
       coff[s][e] = csr_reg ? (o0 | (o1 << 16)) : 0u;
     }
+  const R *nu_half = cnu + srow * dstride + half * kHalf;
 
   // range-switch temperatures of the lane's species and reactions, held in
   // registers so that the choice of coefficient set needs no LDS round trip
@@ -814,7 +829,16 @@ stev_persistent(const KArgs a) {
     for (int s = 0; s < SPL; ++s) {
       const R *nu = cnu + kk[s] * dstride;
       R om = R(0);
-      if (csr_reg) {
+      if (kSplitRow && split) {
+#pragma unroll
+        for (int e = 0; e < kHalf; ++e) {
+          const unsigned o = (e & 1) ? (coff[s][e >> 1] >> 16) : (coff[s][e >> 1] & 0xffffu);
+          om += nu_half[e] * sQ[o];
+        }
+        R oa, ob;
+        swap_pair<32>(om, oa, ob);
+        om = half ? R(0) : oa + ob;   // upper lanes hold no species (n_s <= 32)
+      } else if (csr_reg) {
         // fixed trip count, no branches: all loads issue back to back; the
         // padding adds nu = 0 times the zero entry, which leaves om unchanged
 #pragma unroll

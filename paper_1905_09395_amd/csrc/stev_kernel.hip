@@ -36,13 +36,19 @@ constexpr double kCos13[7] = {1.0, 0.8854560256532099, 0.5680647467311558,
 constexpr double kSin13[7] = {0.0, 0.46472317204376856, 0.8229838658936564,
                               0.992708874098054, 0.9350162426854148,
                               0.6631226582407952, 0.23931566428755777};
-// coefficient of (x_m + x_{13-m}) in Re X_k
-__host__ __device__ constexpr double tw_re(int k, int m) {
-  return ((k * m) % 13) <= 6 ? kCos13[(k * m) % 13] : kCos13[13 - (k * m) % 13];
-}
-// coefficient of (x_m - x_{13-m}) in Im X_k (= -sin(2 pi k m / 13))
-__host__ __device__ constexpr double tw_im(int k, int m) {
-  return ((k * m) % 13) <= 6 ? -kSin13[(k * m) % 13] : kSin13[13 - (k * m) % 13];
+
+// Holds a wave-uniform FP64 value in a VGPR pair.  An FP64 constant is no
+// inline operand, so kept in scalar registers it occupies a pair there, and
+// the integration kernel runs out of them: the compiler then rebuilds such
+// constants with two scalar moves per use and spills other scalars to VGPR
+// lanes.  A lone wave issues one instruction per four cycles whatever its
+// kind, so those moves cost as much as the arithmetic.  FP32 constants are
+// inline literals and stay as they are; kernels without VGPR headroom (ON
+// false) leave the choice to the compiler.
+template <bool ON, typename R>
+__device__ __forceinline__ R in_vgpr(R x) {
+  if constexpr (ON && sizeof(R) == 8) asm volatile("" : "+v"(x));
+  return x;
 }
 
 __device__ __forceinline__ void wave_lds_sync() {
@@ -470,12 +476,23 @@ stev_persistent(const KArgs a) {
 #pragma unroll
   for (int r = 0; r < RPL; ++r) tmid_r[r] = rxR[jj[r] * kRxStride + RX_TMID];
 
-  const R ystep = R(a.ystep), alpha = R(a.alpha);
-  const R tol_ring2 = R(a.tol_ring2), tol_freq = R(a.tol_freq);
-  const R r_fac = R(a.r_fac), r_fac_inv = R(a.r_fac_inv), rof_min = R(a.rof_min);
+  // uniform FP64 parameters and twiddles in VGPRs: in the one-cell-per-wave
+  // kernel with one reaction per lane, which has the registers to spare
+  constexpr bool kVc = (G == 64) && (RRPL == 1);
+  const R ystep = in_vgpr<kVc>(R(a.ystep)), alpha = in_vgpr<kVc>(R(a.alpha));
+  const R tol_ring2 = in_vgpr<kVc>(R(a.tol_ring2)), tol_freq = in_vgpr<kVc>(R(a.tol_freq));
+  const R r_fac = in_vgpr<kVc>(R(a.r_fac)), r_fac_inv = in_vgpr<kVc>(R(a.r_fac_inv));
+  const R rof_min = in_vgpr<kVc>(R(a.rof_min));
   const R ln_patm_r = R(a.ln_patm_r);
   const R rgas = R(kRgas);
   const double tf = a.tf, dtmax = a.dtmax;
+  // the distinct DFT twiddles cos, sin(2 pi j / 13), j = 1..6
+  R twc[6], tws[6];
+#pragma unroll
+  for (int j = 0; j < 6; ++j) {
+    twc[j] = in_vgpr<kVc>(R(kCos13[j + 1]));
+    tws[j] = in_vgpr<kVc>(R(kSin13[j + 1]));
+  }
 
   // per-cell state (replicated over the group where scalar)
   long long cell = -1;   // index inside batch cb
@@ -626,8 +643,15 @@ stev_persistent(const KArgs a) {
           R re = ring[r][0], im = R(0);
 #pragma unroll
           for (int mm = 0; mm < 6; ++mm) {
-            re += sp[mm] * R(tw_re(k, mm + 1));
-            im += dm[mm] * R(tw_im(k, mm + 1));
+            // cos(2 pi k m / 13) and -sin(2 pi k m / 13) through j = k m mod 13
+            const int j = (k * (mm + 1)) % 13;
+            if (j <= 6) {
+              re += sp[mm] * twc[j - 1];
+              im -= dm[mm] * tws[j - 1];
+            } else {
+              re += sp[mm] * twc[12 - j];
+              im += dm[mm] * tws[12 - j];
+            }
           }
           M2 = fmax(M2, re * re + im * im);
         }

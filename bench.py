@@ -269,8 +269,9 @@ def run_batched(args):
         Pc = torch.cat([b["P"] for b in sel])
         Yc = torch.cat([b["Y0"] for b in sel])
         tuned[k] = ctx.autotune(gm, Tc, Pc, Yc, dt, stev.default_params(precision=prec))
-    # one set of launch parameters serves the call: the larger mechanism's
-    prm = tuned[19]
+    # the call leaves the launch shape on auto: each mechanism's launch takes
+    # the shape tuned (and cached in the context) for it
+    prm = stev.default_params(precision=prec)
 
     def restore():
         for b in B:

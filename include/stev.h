@@ -159,7 +159,11 @@ int stev_integrate(stev_ctx *ctx, const stev_mech *mech, int64_t n_cells,
  * rules of stev_integrate with its own T[b], P[b], Y[b], ld_cell[b],
  * ld_species[b], iters_out[b], status_out[b] (the last two arrays and their
  * entries may be NULL).  Device pointers only.  Every batch uses `params`
- * (its precision selects the pointer types).  With params->use_graph the
+ * (its precision selects the pointer types); the launch-shape fields
+ * lanes_per_cell, waves_per_wg and compact_every that are 0 (auto) are set
+ * per mechanism from the shape stev_autotune cached for that mechanism and
+ * the total cell count of its batches (same log2 bucket), when there is one,
+ * and otherwise chosen as in stev_integrate.  With params->use_graph the
  * launch sequence is recorded as a HIP graph on first use and replayed when
  * the same call (same pointers, sizes, mechanisms and parameters) repeats;
  * up to 8 such sequences are kept per context.  stats aggregates all
@@ -298,8 +302,13 @@ int stev_thermo_eval(stev_ctx *ctx, const stev_mech *mech, int32_t thermo, int64
  * species-major with ld_cell == 1).  Only the fields that are 0 (auto) in
  * *inout are tuned; the others are kept and the result is written back into
  * *inout.  Results are cached per context by (mechanism shape, precision,
- * thermo, dft_window, log2 of n_cells): a cache hit runs nothing.  Results of
- * an integration do not depend on these fields, only its time does. */
+ * thermo, dft_window, log2 of n_cells): a cache hit runs nothing, and
+ * stev_integrate_batched reads the cache for its auto fields.  waves_per_wg
+ * and compact_every change the time of an integration, never its results;
+ * lanes_per_cell selects the kernel variant, and variants order their sums
+ * over lanes differently, so they agree to rounding (each is held to the
+ * oracle's tolerances), while one variant gives the same bits for any
+ * launch shape. */
 int stev_autotune(stev_ctx *ctx, const stev_mech *mech, int64_t n_cells, const void *T,
                   const void *P, const void *Y, int64_t ld_cell, int64_t ld_species,
                   double dt_flow, stev_params *inout);

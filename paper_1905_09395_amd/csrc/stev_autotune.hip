@@ -3,8 +3,9 @@
 // (how many iterations pass between compaction/refill attempts, Sec 2.4).
 // Trials integrate a private copy of the caller's cells; every trial starts
 // from the same state, and since a cell's result does not depend on the
-// launch shape only the time differs.  Coordinate descent: lanes per cell,
-// then waves, then cadence.  Results are cached per (mechanism shape,
+// launch shape only the time differs.  Search: lanes per cell by waves per
+// workgroup as a grid, then the cadence, then lanes per cell again at the
+// chosen waves and cadence.  Results are cached per (mechanism shape,
 // precision, thermo, size bucket).
 #include <hip/hip_runtime.h>
 
@@ -35,6 +36,15 @@ std::string tune_key(const stev_mech *m, const stev_params &p, long long n) {
 
 }  // namespace
 
+void apply_tuned(stev_ctx *ctx, const stev_mech *m, stev_params &p, long long n_cells) {
+  if (p.lanes_per_cell != 0 && p.waves_per_wg != 0 && p.compact_every != 0) return;
+  auto hit = ctx->tune_cache.find(tune_key(m, p, n_cells));
+  if (hit == ctx->tune_cache.end()) return;
+  if (p.lanes_per_cell == 0) p.lanes_per_cell = hit->second.lanes_per_cell;
+  if (p.waves_per_wg == 0) p.waves_per_wg = hit->second.waves_per_wg;
+  if (p.compact_every == 0) p.compact_every = hit->second.compact_every;
+}
+
 extern "C" int stev_autotune(stev_ctx *ctx, const stev_mech *m, int64_t n_cells, const void *T,
                              const void *P, const void *Y, int64_t ld_cell, int64_t ld_species,
                              double dt_flow, stev_params *inout) {
@@ -48,6 +58,8 @@ extern "C" int stev_autotune(stev_ctx *ctx, const stev_mech *m, int64_t n_cells,
   int rc = validate_params(ctx, m, p, dt_flow);
   if (rc) return rc;
   const std::string key = tune_key(m, p, n_cells);
+  (void)hipSetDevice(ctx->device);
+  std::lock_guard<std::mutex> guard(ctx->call_mu);
   {
     auto hit = ctx->tune_cache.find(key);
     if (hit != ctx->tune_cache.end()) {
@@ -57,8 +69,6 @@ extern "C" int stev_autotune(stev_ctx *ctx, const stev_mech *m, int64_t n_cells,
       return STEV_OK;
     }
   }
-  (void)hipSetDevice(ctx->device);
-  std::lock_guard<std::mutex> guard(ctx->call_mu);
   hipStream_t s = ctx->stream;
   const long long n = std::min<long long>(n_cells, kMaxTuneCells);
   const size_t rsz = p.precision == STEV_F64 ? 8 : 4;
@@ -151,12 +161,18 @@ extern "C" int stev_autotune(stev_ctx *ctx, const stev_mech *m, int64_t n_cells,
     }
     return STEV_OK;
   };
+  // lanes per cell and waves per workgroup interact through occupancy, so
+  // they are searched as a grid; then the cadence; then lanes per cell once
+  // more at the chosen waves and cadence
   for (int G : Gs)
-    if ((rc = consider({G, Ws.front(), Ks.front()}))) break;
-  if (!rc)
-    for (size_t i = 1; i < Ws.size() && !rc; ++i) rc = consider({best.G, Ws[i], best.K});
+    for (size_t i = 0; i < Ws.size() && !rc; ++i) rc = consider({G, Ws[i], Ks.front()});
   if (!rc)
     for (size_t i = 1; i < Ks.size() && !rc; ++i) rc = consider({best.G, best.waves, Ks[i]});
+  if (!rc) {
+    const Trial at = best;
+    for (int G : Gs)
+      if (G != at.G && !rc) rc = consider({G, at.waves, at.K});
+  }
   cleanup();
   if (rc) return rc;
   stev_params tuned = p;

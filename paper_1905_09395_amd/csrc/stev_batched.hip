@@ -80,8 +80,12 @@ int ml_build(stev_ctx *ctx, MultiLaunch &ml, hipStream_t s) {
   size_t slot = 0;
   for (size_t g = 0; g < n_groups; ++g) {
     MultiLaunch::Grp &G = ml.groups[g];
-    if ((rc = plan_launch(ctx, G.m, ml.p, G.cells, G.lp))) return rc;
-    if ((rc = fill_kargs(ctx, G.m, ml.p, ml.dt, G.a))) return rc;
+    // launch-shape fields the caller left on auto take this mechanism's
+    // tuned shape (cached by stev_autotune for its cell count), if any
+    stev_params q = ml.p;
+    apply_tuned(ctx, G.m, q, G.cells);
+    if ((rc = plan_launch(ctx, G.m, q, G.cells, G.lp))) return rc;
+    if ((rc = fill_kargs(ctx, G.m, q, ml.dt, G.a))) return rc;
     const size_t first = slot;
     long long begin = 0;
     for (int i : G.idx) {

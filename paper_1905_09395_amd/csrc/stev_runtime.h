@@ -167,6 +167,10 @@ void dev_free(stev_ctx *ctx, void *p, size_t bytes);
 bool is_device_ptr(const void *p);
 int pick_variant(const stev_mech *m, int precision, int want_G);
 int validate_params(stev_ctx *ctx, const stev_mech *m, const stev_params &p, double dt_flow);
+// Fills the launch-shape fields of p left at 0 (auto) from the shape that
+// stev_autotune cached for this mechanism, precision and cell-count bucket,
+// if there is one.  Caller holds ctx->call_mu.
+void apply_tuned(stev_ctx *ctx, const stev_mech *m, stev_params &p, long long n_cells);
 int plan_launch(stev_ctx *ctx, const stev_mech *m, const stev_params &p, long long n_cells,
                 LaunchPlan &lp);
 int fill_kargs(stev_ctx *ctx, const stev_mech *m, const stev_params &p, double dt_flow,

@@ -10,6 +10,7 @@ import pytest
 
 import oracle
 from paper_1905_09395_amd import stev, synth
+from tests import tiny_mechs as tm
 from tests.gpu_common import judge, oracle_ensemble, run_gpu, say
 
 pytestmark = pytest.mark.gpu
@@ -48,6 +49,22 @@ def test_mech6_full_config(ctx, m6, prec):
     assert g["stats"]["total_iters"] == g["iters"].sum()
     assert g["stats"]["max_cell_iters"] == g["iters"].max()
     judge(g, o, prec, f"mech6/{prec}")
+
+
+@pytest.mark.parametrize("prec", [stev.F64, stev.F32])
+def test_bfer_table1_paper_kinetics(ctx, prec):
+    """The paper's own two-step methane kinetics (Table 1 constants, orders
+    0.5 / 0.65 of Eq 28, the T^0.7 and reversible term of Eqs 29-30) on the
+    1024-cell methane field."""
+    m = tm.bfer_table1()
+    gm = ctx.mechanism(m)
+    T, P, Y = synth.make_cells_mech6()
+    say(f"BFER (Table 1) 1024 cells prec={prec}")
+    o = oracle_ensemble(oracle.OracleMech(m), T, P, Y, DT, prec)
+    g = run_gpu(ctx, gm, T, P, Y, DT, prec)
+    say(f"  iterations: max {g['iters'].max()}, total {g['iters'].sum()}")
+    judge(g, o, prec, f"bfer/{prec}")
+    gm.close()
 
 
 @pytest.mark.parametrize("prec", [stev.F64, stev.F32])

@@ -599,3 +599,69 @@ def test_eq25_cap_holds_stiff_equilibrium_at_marginal_stability(orc):
     h_l = h[-1]
     expected = dev * (-1.0) ** (n - 1) * (1.0 - h_l * (kf + kr))
     assert capped["Y"][0] - ya_eq == pytest.approx(expected, rel=1e-6, abs=1e-15)
+
+
+# ----------------------------------------------------------------------------
+# The paper's BFER kinetics (Table 1 constants, Eqs 26-29) from the golden
+# fixture tests/golden/bfer_table1.json
+# ----------------------------------------------------------------------------
+CAL = 4.184
+
+
+def test_bfer_table1_temperature_dependence(orc):
+    """MEPOX alone consumes CH4; with no CH4 and no CO2, COROX's forward rate
+    alone consumes CO.  At fixed mass fractions and pressure, C = rho Y / W
+    with rho proportional to 1/T, so dY/dt ~ k(T) T^(1 - sum of orders): the
+    ratio of rates at two temperatures follows from the printed activation
+    energies, the T^0.7 of Eq 29 and the orders of Eqs 28-29 alone."""
+    om = orc.OracleMech(tm.bfer_table1())
+    T1, T2 = 1300.0, 1900.0
+    # species order CH4, O2, CO, CO2, H2O, N2
+    Y = np.array([0.05, 0.2, 0.0, 0.0, 0.0, 0.75])
+    s1 = orc.source(om, T1, P1, Y, alpha=0.0)["dYdt"][0]
+    s2 = orc.source(om, T2, P1, Y, alpha=0.0)["dYdt"][0]
+    assert s1 < 0.0
+    assert s1 / s2 == pytest.approx(
+        math.exp(-35500.0 * CAL / R_SI * (1 / T1 - 1 / T2)) * (T1 / T2) ** (1.0 - 1.15), rel=1e-12)
+    Y = np.array([0.0, 0.2, 0.05, 0.0, 0.0, 0.75])
+    c1 = orc.source(om, T1, P1, Y, alpha=0.0)["dYdt"][2]
+    c2 = orc.source(om, T2, P1, Y, alpha=0.0)["dYdt"][2]
+    assert c1 < 0.0
+    assert c1 / c2 == pytest.approx(
+        (T1 / T2) ** 0.7 * math.exp(-12000.0 * CAL / R_SI * (1 / T1 - 1 / T2))
+        * (T1 / T2) ** (1.0 - 1.5), rel=1e-12)
+
+
+def test_bfer_table1_units(orc):
+    """The printed k are in cm-mol-s units: for total order n the SI rate
+    constant is k (1e-6)^(n - 1) (m^3 per cm^3).  The initial CH4 rate of
+    MEPOX (Eq 28) at a given state, from the ideal-gas density and the
+    printed constants."""
+    m = tm.bfer_table1()
+    om = orc.OracleMech(m)
+    T = 1500.0
+    Y = np.array([0.05, 0.2, 0.0, 0.0, 0.0, 0.75])
+    W = m["W"]
+    rho = P1 / (R_SI * T * np.sum(Y / W))
+    C = rho * Y / W
+    k_si = 4.9e9 * (1e-6) ** (1.15 - 1.0) * math.exp(-35500.0 * CAL / (R_SI * T))
+    r = k_si * C[0] ** 0.5 * C[1] ** 0.65
+    s = orc.source(om, T, P1, Y, alpha=0.0)["dYdt"]
+    assert s[0] == pytest.approx(-W[0] * r / rho, rel=1e-12)
+    # Eq 26 stoichiometry: O2 at 1.5 and H2O at 2 times the CH4 molar rate
+    assert s[1] / W[1] == pytest.approx(1.5 * s[0] / W[0], rel=1e-12)
+    assert s[4] / W[4] == pytest.approx(-2.0 * s[0] / W[0], rel=1e-12)
+
+
+def test_bfer_table1_invariants(orc):
+    """Integrating the paper's mechanism over one flow step: mass fractions
+    sum to one and C, H, O and N are conserved (Eqs 26-27 balance)."""
+    m = tm.bfer_table1()
+    T, P, Y = synth.make_cells_mech6(64, seed=17)
+    r = orc.integrate(orc.OracleMech(m), T, P, Y, 1e-4)
+    assert np.all(r["status"] == 0)
+    np.testing.assert_allclose(r["Y"].sum(axis=1), 1.0, atol=1e-12)
+    e0 = _element_totals(m, Y)
+    e1 = _element_totals(m, r["Y"])
+    np.testing.assert_allclose(e1, e0, rtol=1e-11, atol=1e-11 * np.abs(e0).max())
+    assert np.any(r["iters"] > 50)

@@ -65,3 +65,27 @@ def dissoc_a2b(kf, a7_A, a7_B, WA=0.032):
     elem = np.zeros((2, 4), dtype=int)
     return pack_mechanism("a2b", ["A", "B"], elem, lo, lo.copy(), rx,
                           W=np.array([WA, WA / 2.0]))
+
+
+def bfer_table1():
+    """The paper's two-step BFER methane mechanism: kinetics from the cited
+    fixture (Table 1 constants, Eqs 26-29 forms; cm-mol-s units, calories),
+    on the synthetic NASA-7 thermo of the 6-species set (the paper prints no
+    thermo data), N2 inert."""
+    import json
+    import os
+    from paper_1905_09395_amd import synth
+    with open(os.path.join(os.path.dirname(__file__), "golden", "bfer_table1.json")) as f:
+        fx = json.load(f)
+    m6 = synth.make_mech6()
+    names = list(m6["species"])
+    ix = {s: i for i, s in enumerate(names)}
+    rx = []
+    for name in ("MEPOX", "COROX"):
+        r = fx["reactions"][name]
+        rx.append(dict(reac={ix[s]: v for s, v in r["reactants"].items()},
+                       prod={ix[s]: v for s, v in r["products"].items()},
+                       rev=r["reversible"],
+                       forder={ix[s]: v for s, v in r["orders"].items()},
+                       A=r["k"], b=r["T_exponent"], Ea=r["Ea_cal_per_mol"] * 4.184))
+    return pack_mechanism("bfer", names, m6["elem"], m6["nasa_lo"], m6["nasa_hi"], rx)

@@ -93,13 +93,19 @@ typedef struct {
                              [-127, 127] and thermo = STEV_THERMO_POLY,
                              else STEV_EINVAL */
   int32_t hot_first;      /* stev_integrate: hand cells to the workgroups
-                             hottest first (1, default) or in array order
-                             (0).  Igniting cells take the most steps and the
-                             longest of them sets the time of a field; the
-                             order changes scheduling only, never a cell's
-                             result.  Fields under 4096 cells keep array
-                             order; the order takes 4 * n_cells + 512 bytes
-                             of the context's device scratch */
+                             hottest first (1), hottest first with the first
+                             16384 cells of that order re-sorted by the step
+                             counts of a probe integration of private copies
+                             of them over 1 % of dt_flow (2, default), or in
+                             array order (0).  Igniting cells take the most
+                             steps and the longest of them sets the time of
+                             a field; the order changes scheduling only,
+                             never a cell's result or the call's statistics
+                             (the probe's kernel time is part of kernel_ms).
+                             Fields under 4096 cells keep array order; the
+                             order takes 4 * n_cells + 512 bytes of the
+                             context's device scratch, the probe about
+                             16384 * (n_species + 4) * 8 bytes more */
   int32_t reserved;
 } stev_params;
 

@@ -145,7 +145,7 @@ struct stev_ctx {
   std::string err;
   unsigned long long *ctl = nullptr;       // device control words
   unsigned long long *ctl_host = nullptr;  // pinned mirror
-  Scratch sT, sP, sY, sI, sS, sIdx;
+  Scratch sT, sP, sY, sI, sS, sIdx, sProbe;
   ServeState *serve = nullptr;
   std::map<std::string, stev_params> tune_cache;
   // multi-batch launches: side streams for mechanism groups, fork/join events
@@ -177,6 +177,11 @@ int fill_kargs(stev_ctx *ctx, const stev_mech *m, const stev_params &p, double d
                stev::KArgs &a);
 int launch_zero(stev_ctx *ctx, unsigned long long *p, int n, hipStream_t s);
 int launch_stev(stev_ctx *ctx, const LaunchPlan &lp, stev::KArgs &a, hipStream_t s);
+// Re-sorts the first cells of the dispatch order idx (a permutation of the
+// launch a's cells) by the iteration counts of a short probe integration of
+// private copies of them, costliest first; enqueued on s.
+int probe_refine_order(stev_ctx *ctx, const stev_mech *m, const stev_params &p,
+                       const stev::KArgs &a, int *idx, hipStream_t s);
 
 // thermo network (stev_mlp.hip)
 void mlp_release(stev_ctx *ctx, stev_mech *m);

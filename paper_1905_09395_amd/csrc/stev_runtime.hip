@@ -121,7 +121,7 @@ extern "C" void stev_default_params(stev_params *p) {
   p->compact_every = 0;
   p->grid_wgs = 0;
   p->use_graph = 1;
-  p->hot_first = 1;
+  p->hot_first = 2;
 }
 
 extern "C" int stev_init(stev_ctx **out, int hip_device, size_t hbm_budget_bytes) {
@@ -202,7 +202,8 @@ extern "C" void stev_shutdown(stev_ctx *ctx) {
     if (ctx->ev_join[i]) (void)hipEventDestroy(ctx->ev_join[i]);
   }
   if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
-  for (auto *s : {&ctx->sT, &ctx->sP, &ctx->sY, &ctx->sI, &ctx->sS, &ctx->sIdx}) s->release(ctx);
+  for (auto *s : {&ctx->sT, &ctx->sP, &ctx->sY, &ctx->sI, &ctx->sS, &ctx->sIdx, &ctx->sProbe})
+    s->release(ctx);
   dev_free(ctx, ctx->ctl, 64 * sizeof(unsigned long long));
   if (ctx->ctl_host) (void)hipHostFree(ctx->ctl_host);
   if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
@@ -671,8 +672,8 @@ int validate_params(stev_ctx *ctx, const stev_mech *m, const stev_params &p, dou
     return stev_fail(ctx, STEV_EINVAL, "lanes_per_cell out of range");
   if (p.thermo == STEV_THERMO_MLP && !m->mlp.enabled)
     return stev_fail(ctx, STEV_EINVAL, "thermo=MLP but no network attached to the mechanism");
-  if (p.hot_first != 0 && p.hot_first != 1)
-    return stev_fail(ctx, STEV_EINVAL, "hot_first must be 0 or 1");
+  if (p.hot_first < 0 || p.hot_first > 2)
+    return stev_fail(ctx, STEV_EINVAL, "hot_first must be 0, 1 or 2");
   if (p.stab_limit != 0 && p.stab_limit != 1)
     return stev_fail(ctx, STEV_EINVAL, "stab_limit must be 0 or 1");
   if (p.stab_limit && p.thermo != STEV_THERMO_POLY)
@@ -838,6 +839,7 @@ extern "C" int stev_integrate(stev_ctx *ctx, const stev_mech *m, int64_t n_cells
     HIP_TRY(hipLaunchKernel(kOrderOffsets, dim3(1), dim3(64), oargs, 0, s));
     void *pargs[] = {&T_arg, &n_arg, &bins, &idx};
     HIP_TRY(hipLaunchKernel(kOrderPlace[p.precision], dim3(grid), dim3(256), pargs, 0, s));
+    if (p.hot_first == 2 && (rc = probe_refine_order(ctx, m, p, a, idx, s))) return rc;
     a.cell_index = idx;
     // one workgroup per CU starts from the cold end of the order, the rest
     // take the hottest cells first: the longest cells are not all queued

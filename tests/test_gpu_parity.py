@@ -209,21 +209,23 @@ def test_results_independent_of_launch_shape(ctx, m19, m6, prec):
 
 @pytest.mark.parametrize("prec", [stev.F64, stev.F32])
 def test_hot_first_order_changes_no_result(ctx, m19, prec):
-    """The hottest-first dispatch order (fields of 4096 cells and more) only
-    reorders the work: every cell's result, iteration count and status are
-    those of array order, a failed cell is reported at its own index, and the
-    iteration totals agree."""
+    """The hottest-first dispatch order (fields of 4096 cells and more), with
+    or without the probe refinement, only reorders the work: every cell's
+    result, iteration count and status are those of array order, a failed
+    cell is reported at its own index, and the call's statistics agree (the
+    probe's own iterations are not counted)."""
     m, gm, om = m19
     T, P, Y = synth.make_cells_mech19(9001, seed=43)
     T[4321] = np.nan                       # lands in the coldest bin, fails
     say(f"hot-first order 9001 cells prec={prec}")
     a = run_gpu(ctx, gm, T, P, Y, DT, prec, hot_first=0, allow_failed=True)
-    b = run_gpu(ctx, gm, T, P, Y, DT, prec, hot_first=1, allow_failed=True)
-    assert a["rc"] == b["rc"] == stev.STEV_ECELLS
     assert np.flatnonzero(a["status"]).tolist() == [4321]
-    for k in ("iters", "status"):
-        assert np.array_equal(a[k], b[k]), k
     ok = np.isfinite(a["T"])
-    assert np.array_equal(a["T"][ok], b["T"][ok]) and np.array_equal(a["Y"][ok], b["Y"][ok])
-    for k in ("total_iters", "max_cell_iters", "n_failed"):
-        assert a["stats"][k] == b["stats"][k], k
+    for mode in (1, 2):   # temperature buckets; the same refined by a probe
+        b = run_gpu(ctx, gm, T, P, Y, DT, prec, hot_first=mode, allow_failed=True)
+        assert a["rc"] == b["rc"] == stev.STEV_ECELLS
+        for k in ("iters", "status"):
+            assert np.array_equal(a[k], b[k]), (mode, k)
+        assert np.array_equal(a["T"][ok], b["T"][ok]) and np.array_equal(a["Y"][ok], b["Y"][ok])
+        for k in ("total_iters", "max_cell_iters", "n_failed"):
+            assert a["stats"][k] == b["stats"][k], (mode, k)

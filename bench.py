@@ -114,7 +114,9 @@ def traffic_summary(fetch_csv, write_csv, precision, cells):
     import csv
 
     def read(path, counter):
-        copy, stev = [], []
+        # the integration launch is the last stev_persistent dispatch of the
+        # step (a probe launch of the dispatch-order refinement precedes it)
+        copy, stev = [], {}
         with open(path) as f:
             for row in csv.DictReader(f):
                 if row["Counter_Name"] != counter:
@@ -123,9 +125,10 @@ def traffic_summary(fetch_csv, write_csv, precision, cells):
                 if "copyBuffer" in row["Kernel_Name"]:
                     copy.append(v)
                 elif "stev_persistent" in row["Kernel_Name"]:
-                    stev.append(v)
-        assert copy and len(stev) == 1, f"{path}: expected copies and one integration launch"
-        return max(copy), stev[0]
+                    d = int(row["Dispatch_Id"])
+                    stev[d] = stev.get(d, 0.0) + v
+        assert copy and 1 <= len(stev) <= 2, f"{path}: expected copies and the step's launches"
+        return max(copy), stev[max(stev)]
 
     fc, fs = read(fetch_csv, "FETCH_SIZE")
     wc, ws = read(write_csv, "WRITE_SIZE")
@@ -176,10 +179,14 @@ def pmc_summary(csv_paths, precision, cells):
     import csv
     vals = {}
     for path in csv_paths:
+        per = {}   # dispatch -> counters; the integration launch is the last
         with open(path) as f:
             for row in csv.DictReader(f):
                 if "stev_persistent" in row["Kernel_Name"]:
-                    vals[row["Counter_Name"]] = float(row["Counter_Value"])
+                    c = per.setdefault(int(row["Dispatch_Id"]), {})
+                    c[row["Counter_Name"]] = c.get(row["Counter_Name"], 0.0) + float(row["Counter_Value"])
+        if per:
+            vals.update(per[max(per)])
     base = os.path.join(ROOT, "profiles", f"stev_pmc_{precision}_mech19_{cells}")
     with open(base + ".md", "w") as f:
         f.write(f"# Counters of one stev_persistent launch ({precision}, 19 species, {cells} cells)\n\n")

@@ -18,6 +18,9 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "stev_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
+# a mutated build of the same sources (tests/test_oracle_mutations.py) is
+# loaded in a child process through this variable; nothing else sets it
+_LIB_OVERRIDE = os.environ.get("STEV_ORACLE_LIB")
 _lib = None
 
 
@@ -57,9 +60,12 @@ DEFAULT_PARAMS = dict(ystep_max=1e-3, delta_max=1e-2, alpha=1e-5, tol_ring=0.5,
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB):
-            build()
-        L = C.CDLL(_LIB)
+        if _LIB_OVERRIDE:
+            L = C.CDLL(_LIB_OVERRIDE)
+        else:
+            if not os.path.exists(_LIB):
+                build()
+            L = C.CDLL(_LIB)
         dp = C.POINTER(C.c_double)
         L.orc_thermo.argtypes = [C.POINTER(_Mech), C.c_int, C.c_double, dp]
         L.orc_ystarstar.argtypes = [C.c_double, C.c_double]

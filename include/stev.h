@@ -126,6 +126,17 @@ typedef struct {
   double queued_ms;       /* serving: submit -> admission (launch) */
   int32_t budget_waits;   /* serving: admission attempts refused for lack of HBM budget */
   int32_t round_requests; /* serving: requests that shared this request's launch */
+  double launch_ms;       /* stev_integrate(_noalloc): HIP-event time of the
+                             integration launch alone (kernel_ms less the
+                             dispatch-order kernels and the probe) */
+  /* Sec 2.4 load (stev_integrate and stev_integrate_noalloc; zero from the
+   * other entry points): cells by iteration count.  Bin b < 4 holds the
+   * cells of exactly b iterations; a count in [2^e, 2^(e+1)), e >= 2, lies
+   * in bin 4(e-1) + k with k the two bits below its leading one, so bin
+   * b >= 4 starts at 2^e + k 2^(e-2) with e = b/4 + 1, k = b%4.  The
+   * active load at iteration i (cells still integrating in their i-th
+   * step, i >= 1) is the number of cells with at least i iterations. */
+  int64_t load_hist[128];
 } stev_stats;
 
 void stev_default_params(stev_params *p);
@@ -182,11 +193,17 @@ int stev_integrate_batched(stev_ctx *ctx, int32_t n_batches, const stev_mech *co
                            int32_t *const *iters_out, uint8_t *const *status_out,
                            stev_stats *stats);
 
-/* Serving: enqueue one solve; returns at once with a ticket.  Device
- * pointers only; arrays must stay valid and untouched until stev_poll
- * returns STEV_OK.  Admission is by the HBM budget: a request whose work
- * buffers can never fit returns STEV_ENOMEM; one that does not fit now is
- * queued.  Thread-safe with respect to stev_poll. */
+/* Serving: enqueue one solve; returns at once with a ticket.  T, P, Y and
+ * the optional iters_out / status_out may be host or device pointers (any
+ * mix, as for stev_integrate).  Device arrays are solved in place; host
+ * arrays are staged through device buffers charged to the context's HBM
+ * budget, and their results are copied back before stev_poll reports the
+ * ticket done.  All arrays must stay valid and untouched until stev_poll
+ * returns a terminal code (anything but STEV_EAGAIN).  Admission is by the
+ * HBM budget: a request whose staging can never fit returns STEV_ENOMEM;
+ * one that does not fit now is queued until earlier requests free memory.
+ * stev_submit and stev_poll are thread-safe with respect to each other and
+ * themselves (the serving state is created once, by the first submit). */
 int stev_submit(stev_ctx *ctx, const stev_mech *mech, int64_t n_cells, void *T,
                 const void *P, void *Y, int64_t ld_cell, int64_t ld_species,
                 double dt_flow, const stev_params *params, int32_t *iters_out,

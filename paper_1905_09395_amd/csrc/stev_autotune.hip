@@ -180,6 +180,9 @@ extern "C" int stev_autotune(stev_ctx *ctx, const stev_mech *m, int64_t n_cells,
   tuned.waves_per_wg = best.waves;
   tuned.compact_every = best.K;
   ctx->tune_cache[key] = tuned;
+  // recorded multi-batch launches of this mechanism were planned with the
+  // shape known before this tuning: drop them so the next call re-plans
+  plans_forget(ctx, m);
   inout->lanes_per_cell = best.G;
   inout->waves_per_wg = best.waves;
   inout->compact_every = best.K;

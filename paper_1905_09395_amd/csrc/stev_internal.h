@@ -66,6 +66,23 @@ constexpr int kExpTab = 64;
 constexpr int kLogTab = 32;
 constexpr int kXtabBytes = (2 * kExpTab + 3 * kLogTab) * 8;
 
+// Control words of one field integration: [0, 8) the call's counters (next
+// cell, sum of iterations, max iterations, failed cells), [8, 16) the
+// dispatch-order probe's, then kLoadBins words of the load histogram
+// (Sec 2.4: cells by iteration count, see load_bin), kCtlWords in all.
+constexpr int kLoadBins = 128;
+constexpr int kCtlHist = 16;
+constexpr int kCtlWords = kCtlHist + kLoadBins;
+
+// Histogram bin of a cell's iteration count: counts 0..3 have their own
+// bins; a count in [2^e, 2^(e+1)) (e >= 2) falls in quarter-octave bin
+// 4(e - 1) + k, k = the two bits below the leading one.
+__host__ __device__ inline int load_bin(unsigned it) {
+  if (it < 4u) return (int)it;
+  const int e = 31 - __builtin_clz(it);
+  return 4 * (e - 1) + (int)((it >> (e - 2)) & 3u);
+}
+
 struct MechLayout {
   int n_s, n_r, n_rev, nnz_csr;
   int has_frac;        // a slot carries an order other than 1 (pow needed)
@@ -152,6 +169,8 @@ struct KArgs {
   int dft_on, compact_every;
   // control: [0] next cell, [1] sum iters, [2] max iters, [3] failed cells
   unsigned long long *ctl;
+  // load histogram (kLoadBins words, one count per retired cell), nullable
+  unsigned long long *hist;
   // multi-batch launch: nullptr for one batch given by T..status_out above;
   // otherwise n_batches descriptors sorted by begin (batches[0].begin = 0),
   // and per-batch statistics bstats[4b + {0 sum iters, 1 max iters, 2 failed}]

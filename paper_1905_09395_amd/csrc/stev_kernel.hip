@@ -541,6 +541,7 @@ stev_persistent(const KArgs a) {
           sum_it += it;
           max_it = it > max_it ? it : max_it;
           n_fail += (st != 0);
+          if (a.hist) atomicAdd(&a.hist[load_bin((unsigned)it)], 1ull);   // Sec 2.4 load
           if (cb >= 0) {
             unsigned long long *bs = a.bstats + 4 * cb;
             atomicAdd(&bs[0], (unsigned long long)it);

@@ -68,18 +68,23 @@ __global__ void probe_sort(const int *it, int np, int *idx, int *tmp) {
 
 }  // namespace
 
+size_t probe_scratch_bytes(const stev_mech *m, int precision, long long n_cells) {
+  const long long np = std::min<long long>(n_cells, kProbeCells);
+  const size_t rsz = precision == STEV_F64 ? 8 : 4;
+  return 3 * align256(np * rsz) + align256(np * (size_t)m->n_s * rsz) + 2 * align256(np * 4);
+}
+
 int probe_refine_order(stev_ctx *ctx, const stev_mech *m, const stev_params &p,
-                       const stev::KArgs &a, int *idx, hipStream_t s) {
+                       const stev::KArgs &a, int *idx, void *probe_base,
+                       unsigned long long *probe_ctl, hipStream_t s) {
   const long long np = std::min<long long>(a.n_cells, kProbeCells);
   if (np < 1) return STEV_OK;
   const size_t rsz = p.precision == STEV_F64 ? 8 : 4;
   const size_t ns = (size_t)m->n_s;
   const size_t oT = 0, oP = oT + align256(np * rsz), oY = oP + align256(np * rsz);
   const size_t oI = oY + align256(np * ns * rsz), oX = oI + align256(np * 4);
-  const size_t bytes = oX + align256(np * 4);
-  int rc = ctx->sProbe.ensure(ctx, bytes);
-  if (rc) return rc;
-  char *base = static_cast<char *>(ctx->sProbe.ptr);
+  int rc;
+  char *base = static_cast<char *>(probe_base);
   void *pT = base + oT, *pP = base + oP, *pY = base + oY;
   int *pIt = reinterpret_cast<int *>(base + oI), *tmp = reinterpret_cast<int *>(base + oX);
 
@@ -108,7 +113,8 @@ int probe_refine_order(stev_ctx *ctx, const stev_mech *m, const stev_params &p,
   b.n_front = 0;
   b.tf = a.tf * kProbeFrac;
   b.dtmax = b.tf;
-  b.ctl = ctx->ctl + 8;   // words 8..15: the call's own statistics stay in 0..7
+  b.ctl = probe_ctl;   // the call's own statistics stay in its own words
+  b.hist = nullptr;
   if ((rc = launch_zero(ctx, b.ctl, 8, s))) return rc;
   if ((rc = launch_stev(ctx, lp, b, s))) return rc;
 

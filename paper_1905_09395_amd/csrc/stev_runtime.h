@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <atomic>
+#include <chrono>
 #include <condition_variable>
 #include <deque>
 #include <map>
@@ -139,14 +140,17 @@ struct stev_ctx {
   char arch[64] = {0};
   hipStream_t own_stream = nullptr;
   hipStream_t stream = nullptr;
-  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr;   // call start, end; main launch start
   size_t budget = 0, used = 0;
   std::mutex mem_mu, err_mu, call_mu;
   std::string err;
   unsigned long long *ctl = nullptr;       // device control words
   unsigned long long *ctl_host = nullptr;  // pinned mirror
   Scratch sT, sP, sY, sI, sS, sIdx, sProbe;
-  ServeState *serve = nullptr;
+  // serving state: created once, under serve_mu, by the first stev_submit
+  // and published only once its scheduler runs; read without the lock
+  std::mutex serve_mu;
+  std::atomic<ServeState *> serve{nullptr};
   std::map<std::string, stev_params> tune_cache;
   // multi-batch launches: side streams for mechanism groups, fork/join events
   // and the cache of recorded launch sequences (HIP graphs), keyed by call
@@ -179,9 +183,37 @@ int launch_zero(stev_ctx *ctx, unsigned long long *p, int n, hipStream_t s);
 int launch_stev(stev_ctx *ctx, const LaunchPlan &lp, stev::KArgs &a, hipStream_t s);
 // Re-sorts the first cells of the dispatch order idx (a permutation of the
 // launch a's cells) by the iteration counts of a short probe integration of
-// private copies of them, costliest first; enqueued on s.
+// private copies of them, costliest first; enqueued on s.  The copies live
+// at `base` (probe_scratch_bytes of device memory); the probe launch keeps
+// its statistics in the 8 control words at `ctl`.
 int probe_refine_order(stev_ctx *ctx, const stev_mech *m, const stev_params &p,
-                       const stev::KArgs &a, int *idx, hipStream_t s);
+                       const stev::KArgs &a, int *idx, void *base, unsigned long long *ctl,
+                       hipStream_t s);
+size_t probe_scratch_bytes(const stev_mech *m, int precision, long long n_cells);
+
+// Work buffers of one field integration: kCtlWords control words (the
+// call's counters, the probe's, the load histogram), the dispatch order's
+// bins and index (ordered fields only) and the probe's copies (hot_first ==
+// 2 only).
+struct FieldScratch {
+  unsigned long long *ctl;
+  unsigned long long *bins;
+  int *idx;
+  void *probe;
+};
+int check_integrate_args(stev_ctx *ctx, const stev_mech *m, const stev_params &p,
+                         int64_t n_cells, const void *T, const void *P, const void *Y,
+                         int64_t ld_cell, int64_t ld_species, double dt_flow);
+// the field is handed out in a dispatch order (hot_first)
+bool field_ordered(const stev_params &p, long long n_cells);
+// Enqueues one field integration on s (control words cleared, dispatch order,
+// probe, persistent launch between the context's timing events, statistics
+// copied to ctx->ctl_host); a.n_cells and the state pointers are set.
+int run_field(stev_ctx *ctx, const stev_mech *m, const stev_params &p, const LaunchPlan &lp,
+              stev::KArgs &a, const FieldScratch &ws, hipStream_t s);
+// After the stream has drained: fills stats, STEV_ECELLS if a cell failed.
+int finish_field(stev_ctx *ctx, const LaunchPlan &lp, long long n_cells,
+                 std::chrono::steady_clock::time_point t0, stev_stats *stats);
 
 // thermo network (stev_mlp.hip)
 void mlp_release(stev_ctx *ctx, stev_mech *m);

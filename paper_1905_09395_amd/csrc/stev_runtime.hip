@@ -154,6 +154,7 @@ extern "C" int stev_init(stev_ctx **out, int hip_device, size_t hbm_budget_bytes
   ctx->stream = ctx->own_stream;
   (void)hipEventCreate(&ctx->ev0);
   (void)hipEventCreate(&ctx->ev1);
+  (void)hipEventCreate(&ctx->ev2);
   (void)hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming);
   for (int i = 0; i < stev_ctx::kSide; ++i) {
     if (hipStreamCreateWithFlags(&ctx->side[i], hipStreamNonBlocking) != hipSuccess) {
@@ -162,11 +163,11 @@ extern "C" int stev_init(stev_ctx **out, int hip_device, size_t hbm_budget_bytes
     }
     (void)hipEventCreateWithFlags(&ctx->ev_join[i], hipEventDisableTiming);
   }
-  if (dev_alloc(ctx, (void **)&ctx->ctl, 64 * sizeof(unsigned long long)) != STEV_OK) {
+  if (dev_alloc(ctx, (void **)&ctx->ctl, kCtlWords * sizeof(unsigned long long)) != STEV_OK) {
     stev_shutdown(ctx);
     return STEV_ENOMEM;
   }
-  if (hipHostMalloc((void **)&ctx->ctl_host, 64 * sizeof(unsigned long long)) != hipSuccess) {
+  if (hipHostMalloc((void **)&ctx->ctl_host, kCtlWords * sizeof(unsigned long long)) != hipSuccess) {
     stev_shutdown(ctx);
     return STEV_EDEVICE;
   }
@@ -204,10 +205,11 @@ extern "C" void stev_shutdown(stev_ctx *ctx) {
   if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
   for (auto *s : {&ctx->sT, &ctx->sP, &ctx->sY, &ctx->sI, &ctx->sS, &ctx->sIdx, &ctx->sProbe})
     s->release(ctx);
-  dev_free(ctx, ctx->ctl, 64 * sizeof(unsigned long long));
+  dev_free(ctx, ctx->ctl, kCtlWords * sizeof(unsigned long long));
   if (ctx->ctl_host) (void)hipHostFree(ctx->ctl_host);
   if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
   if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
+  if (ctx->ev2) (void)hipEventDestroy(ctx->ev2);
   if (ctx->own_stream) (void)hipStreamDestroy(ctx->own_stream);
   delete ctx;
 }
@@ -758,21 +760,100 @@ int launch_stev(stev_ctx *ctx, const LaunchPlan &lp, KArgs &a, hipStream_t s) {
 // ---------------------------------------------------------------------------
 // stev_integrate
 // ---------------------------------------------------------------------------
+int check_integrate_args(stev_ctx *ctx, const stev_mech *m, const stev_params &p,
+                         int64_t n_cells, const void *T, const void *P, const void *Y,
+                         int64_t ld_cell, int64_t ld_species, double dt_flow) {
+  if (!m) return stev_fail(ctx, STEV_EINVAL, "null mechanism");
+  if (n_cells < 0) return stev_fail(ctx, STEV_EINVAL, "n_cells < 0");
+  if (n_cells > 0 && (!T || !P || !Y)) return stev_fail(ctx, STEV_EINVAL, "null state array");
+  if (ld_cell < 0 || ld_species < 0) return stev_fail(ctx, STEV_EINVAL, "negative stride");
+  if (n_cells > 1 && ld_cell == 0) return stev_fail(ctx, STEV_EINVAL, "ld_cell == 0");
+  if (m->n_s > 1 && ld_species == 0) return stev_fail(ctx, STEV_EINVAL, "ld_species == 0");
+  return validate_params(ctx, m, p, dt_flow);
+}
+
+bool field_ordered(const stev_params &p, long long n_cells) {
+  return p.hot_first && n_cells >= kOrderMinCells && n_cells <= INT32_MAX;
+}
+
+int run_field(stev_ctx *ctx, const stev_mech *m, const stev_params &p, const LaunchPlan &lp,
+              KArgs &a, const FieldScratch &ws, hipStream_t s) {
+  int rc;
+  a.ctl = ws.ctl;
+  a.hist = ws.ctl + kCtlHist;
+  if ((rc = launch_zero(ctx, ws.ctl, 8, s))) return rc;
+  if ((rc = launch_zero(ctx, a.hist, kLoadBins, s))) return rc;
+  // hottest cells first: a bucket order of the field by temperature, built on
+  // the device, read through a.cell_index by the persistent kernel
+  const bool order = field_ordered(p, a.n_cells);
+  HIP_TRY(hipEventRecord(ctx->ev0, s));
+  if (order) {
+    unsigned long long *bins = ws.bins;
+    int *idx = ws.idx;
+    if ((rc = launch_zero(ctx, bins, kOrderBins, s))) return rc;
+    const void *T_arg = a.T;
+    long long n_arg = a.n_cells;
+    const unsigned grid = (unsigned)std::min<long long>((a.n_cells + 255) / 256, 1024);
+    void *cargs[] = {&T_arg, &n_arg, &bins};
+    HIP_TRY(hipLaunchKernel(kOrderCount[p.precision], dim3(grid), dim3(256), cargs, 0, s));
+    void *oargs[] = {&bins};
+    HIP_TRY(hipLaunchKernel(kOrderOffsets, dim3(1), dim3(64), oargs, 0, s));
+    void *pargs[] = {&T_arg, &n_arg, &bins, &idx};
+    HIP_TRY(hipLaunchKernel(kOrderPlace[p.precision], dim3(grid), dim3(256), pargs, 0, s));
+    if (p.hot_first == 2 &&
+        (rc = probe_refine_order(ctx, m, p, a, idx, ws.probe, ws.ctl + 8, s)))
+      return rc;
+    a.cell_index = idx;
+    // temperature order alone: one workgroup per CU starts from the cold
+    // end of the order, the rest take the hottest cells first, so the
+    // longest cells are not all queued behind one another on the same SIMDs
+    // (measured on the 262144-cell field: fewer slow steps).  With the
+    // probe-refined order the costliest cells are at its front, and every
+    // workgroup takes from there (70.7 against 73.4 ms FP64 on that field)
+    a.n_front = (p.hot_first == 1 && lp.grid > ctx->n_cu) ? lp.grid - ctx->n_cu : 0;
+  }
+  HIP_TRY(hipEventRecord(ctx->ev2, s));
+  if ((rc = launch_stev(ctx, lp, a, s))) return rc;
+  HIP_TRY(hipEventRecord(ctx->ev1, s));
+  HIP_TRY(hipMemcpyAsync(ctx->ctl_host, ws.ctl, kCtlWords * sizeof(unsigned long long),
+                         hipMemcpyDeviceToHost, s));
+  return STEV_OK;
+}
+
+int finish_field(stev_ctx *ctx, const LaunchPlan &lp, long long n_cells,
+                 std::chrono::steady_clock::time_point t0, stev_stats *stats) {
+  float ms = 0.f, lms = 0.f;
+  (void)hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1);
+  (void)hipEventElapsedTime(&lms, ctx->ev2, ctx->ev1);
+  const unsigned long long *c = ctx->ctl_host;
+  if (stats) {
+    stats->launch_ms = lms;
+    for (int b = 0; b < kLoadBins; ++b) stats->load_hist[b] = (int64_t)c[kCtlHist + b];
+    stats->n_cells = n_cells;
+    stats->total_iters = (int64_t)c[1];
+    stats->max_cell_iters = (int64_t)c[2];
+    stats->n_failed = (int64_t)c[3];
+    stats->kernel_ms = ms;
+    stats->lanes_per_cell = lp.G;
+    stats->waves_per_wg = lp.waves;
+    stats->grid_wgs = lp.grid;
+    stats->compact_every = lp.compact;
+    stats->total_ms =
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  }
+  if (c[3] != 0) return stev_fail(ctx, STEV_ECELLS, "%llu cells failed", (unsigned long long)c[3]);
+  return STEV_OK;
+}
+
 extern "C" int stev_integrate(stev_ctx *ctx, const stev_mech *m, int64_t n_cells, void *T,
                               const void *P, void *Y, int64_t ld_cell, int64_t ld_species,
                               double dt_flow, const stev_params *params, int32_t *iters_out,
                               uint8_t *status_out, stev_stats *stats) {
   auto t0 = std::chrono::steady_clock::now();
   if (!ctx) return STEV_EINVAL;
-  if (!m) return stev_fail(ctx, STEV_EINVAL, "null mechanism");
   stev_params p;
   if (params) p = *params; else stev_default_params(&p);
-  if (n_cells < 0) return stev_fail(ctx, STEV_EINVAL, "n_cells < 0");
-  if (n_cells > 0 && (!T || !P || !Y)) return stev_fail(ctx, STEV_EINVAL, "null state array");
-  if (ld_cell < 0 || ld_species < 0) return stev_fail(ctx, STEV_EINVAL, "negative stride");
-  if (n_cells > 1 && ld_cell == 0) return stev_fail(ctx, STEV_EINVAL, "ld_cell == 0");
-  if (m->n_s > 1 && ld_species == 0) return stev_fail(ctx, STEV_EINVAL, "ld_species == 0");
-  int rc = validate_params(ctx, m, p, dt_flow);
+  int rc = check_integrate_args(ctx, m, p, n_cells, T, P, Y, ld_cell, ld_species, dt_flow);
   if (rc) return rc;
   if (stats) std::memset(stats, 0, sizeof(*stats));
   if (n_cells == 0) return STEV_OK;
@@ -801,6 +882,19 @@ extern "C" int stev_integrate(stev_ctx *ctx, const stev_mech *m, int64_t n_cells
   uint8_t *Sd = status_out;
   if (iters_out && !dI) { if ((rc = ctx->sI.ensure(ctx, n_cells * 4))) return rc; Id = (int32_t *)ctx->sI.ptr; }
   if (status_out && !dS) { if ((rc = ctx->sS.ensure(ctx, n_cells))) return rc; Sd = (uint8_t *)ctx->sS.ptr; }
+  // work buffers: the dispatch order and the probe's private copies
+  FieldScratch ws{ctx->ctl, nullptr, nullptr, nullptr};
+  if (field_ordered(p, n_cells)) {
+    if ((rc = ctx->sIdx.ensure(ctx, kOrderBins * sizeof(unsigned long long) +
+                                        (size_t)n_cells * sizeof(int))))
+      return rc;
+    ws.bins = static_cast<unsigned long long *>(ctx->sIdx.ptr);
+    ws.idx = reinterpret_cast<int *>(ws.bins + kOrderBins);
+    if (p.hot_first == 2) {
+      if ((rc = ctx->sProbe.ensure(ctx, probe_scratch_bytes(m, p.precision, n_cells)))) return rc;
+      ws.probe = ctx->sProbe.ptr;
+    }
+  }
   if (!dT) HIP_TRY(hipMemcpyAsync(Td, T, n_cells * rsz, hipMemcpyHostToDevice, s));
   if (!dP) HIP_TRY(hipMemcpyAsync((void *)Pd, P, n_cells * rsz, hipMemcpyHostToDevice, s));
   if (!dY) HIP_TRY(hipMemcpyAsync(Yd, Y, y_extent * rsz, hipMemcpyHostToDevice, s));
@@ -813,67 +907,11 @@ extern "C" int stev_integrate(stev_ctx *ctx, const stev_mech *m, int64_t n_cells
   a.ld_sp = ld_species;
   a.iters_out = Id;
   a.status_out = Sd;
-  a.ctl = ctx->ctl;
-  if ((rc = launch_zero(ctx, ctx->ctl, 8, s))) return rc;
-  // hottest cells first: a bucket order of the field by temperature, built on
-  // the device, read through a.cell_index by the persistent kernel
-  const bool order = p.hot_first && n_cells >= kOrderMinCells && n_cells <= INT32_MAX;
-  int *idx = nullptr;
-  unsigned long long *bins = nullptr;
-  if (order) {
-    if ((rc = ctx->sIdx.ensure(ctx, kOrderBins * sizeof(unsigned long long) +
-                                        (size_t)n_cells * sizeof(int))))
-      return rc;
-    bins = static_cast<unsigned long long *>(ctx->sIdx.ptr);
-    idx = reinterpret_cast<int *>(bins + kOrderBins);
-  }
-  HIP_TRY(hipEventRecord(ctx->ev0, s));
-  if (order) {
-    if ((rc = launch_zero(ctx, bins, kOrderBins, s))) return rc;
-    const void *T_arg = Td;
-    long long n_arg = n_cells;
-    const unsigned grid = (unsigned)std::min<long long>((n_cells + 255) / 256, 1024);
-    void *cargs[] = {&T_arg, &n_arg, &bins};
-    HIP_TRY(hipLaunchKernel(kOrderCount[p.precision], dim3(grid), dim3(256), cargs, 0, s));
-    void *oargs[] = {&bins};
-    HIP_TRY(hipLaunchKernel(kOrderOffsets, dim3(1), dim3(64), oargs, 0, s));
-    void *pargs[] = {&T_arg, &n_arg, &bins, &idx};
-    HIP_TRY(hipLaunchKernel(kOrderPlace[p.precision], dim3(grid), dim3(256), pargs, 0, s));
-    if (p.hot_first == 2 && (rc = probe_refine_order(ctx, m, p, a, idx, s))) return rc;
-    a.cell_index = idx;
-    // temperature order alone: one workgroup per CU starts from the cold
-    // end of the order, the rest take the hottest cells first, so the
-    // longest cells are not all queued behind one another on the same SIMDs
-    // (measured on the 262144-cell field: fewer slow steps).  With the
-    // probe-refined order the costliest cells are at its front, and every
-    // workgroup takes from there (70.7 against 73.4 ms FP64 on that field)
-    a.n_front = (p.hot_first == 1 && lp.grid > ctx->n_cu) ? lp.grid - ctx->n_cu : 0;
-  }
-  if ((rc = launch_stev(ctx, lp, a, s))) return rc;
-  HIP_TRY(hipEventRecord(ctx->ev1, s));
-  HIP_TRY(hipMemcpyAsync(ctx->ctl_host, ctx->ctl, 8 * sizeof(unsigned long long),
-                         hipMemcpyDeviceToHost, s));
+  if ((rc = run_field(ctx, m, p, lp, a, ws, s))) return rc;
   if (!dT) HIP_TRY(hipMemcpyAsync(T, Td, n_cells * rsz, hipMemcpyDeviceToHost, s));
   if (!dY) HIP_TRY(hipMemcpyAsync(Y, Yd, y_extent * rsz, hipMemcpyDeviceToHost, s));
   if (iters_out && !dI) HIP_TRY(hipMemcpyAsync(iters_out, Id, n_cells * 4, hipMemcpyDeviceToHost, s));
   if (status_out && !dS) HIP_TRY(hipMemcpyAsync(status_out, Sd, n_cells, hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
-  float ms = 0.f;
-  (void)hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1);
-  const unsigned long long *c = ctx->ctl_host;
-  if (stats) {
-    stats->n_cells = n_cells;
-    stats->total_iters = (int64_t)c[1];
-    stats->max_cell_iters = (int64_t)c[2];
-    stats->n_failed = (int64_t)c[3];
-    stats->kernel_ms = ms;
-    stats->lanes_per_cell = lp.G;
-    stats->waves_per_wg = lp.waves;
-    stats->grid_wgs = lp.grid;
-    stats->compact_every = lp.compact;
-    stats->total_ms =
-        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-  }
-  if (c[3] != 0) return stev_fail(ctx, STEV_ECELLS, "%llu cells failed", (unsigned long long)c[3]);
-  return STEV_OK;
+  return finish_field(ctx, lp, n_cells, t0, stats);
 }

@@ -286,8 +286,7 @@ void finish_round(stev_ctx *ctx, ServeState *S, Round *rd, int rc) {
   S->busy[rd->slot] = false;
 }
 
-void scheduler(stev_ctx *ctx) {
-  ServeState *S = ctx->serve;
+void scheduler(stev_ctx *ctx, ServeState *S) {
   (void)hipSetDevice(ctx->device);
   std::unique_lock<std::mutex> lk(S->mu);
   while (true) {
@@ -373,8 +372,13 @@ void scheduler(stev_ctx *ctx) {
   }
 }
 
+// Creates the serving state once per context.  Concurrent first submits
+// serialise on serve_mu; the state is published after its scheduler thread
+// has started (the thread gets the state as its argument).
 int serve_start(stev_ctx *ctx) {
-  if (ctx->serve) return STEV_OK;
+  if (ctx->serve.load(std::memory_order_acquire)) return STEV_OK;
+  std::lock_guard<std::mutex> once(ctx->serve_mu);
+  if (ctx->serve.load(std::memory_order_acquire)) return STEV_OK;
   ServeState *S = new ServeState();
   auto undo = [&](int upto) {
     for (int j = 0; j <= upto && j < kSlots; ++j) {
@@ -403,15 +407,16 @@ int serve_start(stev_ctx *ctx) {
       return stev_fail(ctx, STEV_EDEVICE, "serving: pinned allocation failed");
     }
   }
-  ctx->serve = S;
-  S->thr = std::thread(scheduler, ctx);
+  S->thr = std::thread(scheduler, ctx, S);
+  ctx->serve.store(S, std::memory_order_release);
   return STEV_OK;
 }
 
 }  // namespace
 
 void serve_stop(stev_ctx *ctx) {
-  ServeState *S = ctx->serve;
+  std::lock_guard<std::mutex> once(ctx->serve_mu);
+  ServeState *S = ctx->serve.load(std::memory_order_acquire);
   if (!S) return;
   {
     std::lock_guard<std::mutex> g(S->mu);
@@ -431,8 +436,8 @@ void serve_stop(stev_ctx *ctx) {
     dev_free(ctx, S->tab_dev[k], kSlotTableBytes);
     if (S->tab_host[k]) (void)hipHostFree(S->tab_host[k]);
   }
+  ctx->serve.store(nullptr, std::memory_order_release);
   delete S;
-  ctx->serve = nullptr;
 }
 
 extern "C" int stev_submit(stev_ctx *ctx, const stev_mech *m, int64_t n_cells, void *T,
@@ -484,7 +489,7 @@ extern "C" int stev_submit(stev_ctx *ctx, const stev_mech *m, int64_t n_cells, v
     delete r;
     return rc;
   }
-  ServeState *S = ctx->serve;
+  ServeState *S = ctx->serve.load(std::memory_order_acquire);
   {
     std::lock_guard<std::mutex> g(S->mu);
     // never fits: more staging than the budget leaves beside what the
@@ -513,7 +518,7 @@ extern "C" int stev_submit(stev_ctx *ctx, const stev_mech *m, int64_t n_cells, v
 
 extern "C" int stev_poll(stev_ctx *ctx, uint64_t ticket, stev_stats *stats) {
   if (!ctx) return STEV_EINVAL;
-  ServeState *S = ctx->serve;
+  ServeState *S = ctx->serve.load(std::memory_order_acquire);
   if (!S) return stev_fail(ctx, STEV_ENOTFOUND, "unknown ticket %llu", (unsigned long long)ticket);
   Request *r = nullptr;
   {

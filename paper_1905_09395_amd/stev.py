@@ -22,6 +22,31 @@ LIB_PATH = os.path.join(_HERE, "libstev.so")
 HEADER = os.path.join(os.path.dirname(_HERE), "include", "stev.h")
 
 STEV_OK, STEV_EINVAL, STEV_ENOMEM, STEV_EAGAIN, STEV_ENOTFOUND, STEV_EDEVICE, STEV_ECELLS = range(7)
+LOAD_BINS = 128
+
+
+def load_bin_edges():
+    """Lower edge (iteration count) of each bin of Stats.load_hist."""
+    edges = []
+    for b in range(LOAD_BINS):
+        if b < 4:
+            edges.append(b)
+        else:
+            e, k = b // 4 + 1, b % 4
+            edges.append((1 << e) + k * (1 << (e - 2)))
+    return edges
+
+
+def load_curve(load_hist):
+    """Sec 2.4 load from a load histogram: [(i, cells still integrating in
+    their i-th step)] at every bin edge i >= 1 where the load changes."""
+    edges = load_bin_edges()
+    out, tail = [], 0
+    for b in range(LOAD_BINS - 1, 0, -1):
+        tail += int(load_hist[b])
+        if load_hist[b]:
+            out.append((edges[b], tail))
+    return out[::-1]
 F64, F32 = 0, 1
 THERMO_POLY, THERMO_MLP = 0, 1
 ERR_NAMES = {0: "STEV_OK", 1: "STEV_EINVAL", 2: "STEV_ENOMEM", 3: "STEV_EAGAIN",
@@ -61,10 +86,13 @@ class Stats(C.Structure):
                 ("lanes_per_cell", C.c_int32), ("waves_per_wg", C.c_int32),
                 ("grid_wgs", C.c_int32), ("compact_every", C.c_int32),
                 ("latency_ms", C.c_double), ("queued_ms", C.c_double),
-                ("budget_waits", C.c_int32), ("round_requests", C.c_int32)]
+                ("budget_waits", C.c_int32), ("round_requests", C.c_int32),
+                ("launch_ms", C.c_double), ("load_hist", C.c_int64 * 128)]
 
     def as_dict(self):
-        return {f: getattr(self, f) for f, _ in self._fields_}
+        d = {f: getattr(self, f) for f, _ in self._fields_}
+        d["load_hist"] = list(self.load_hist)
+        return d
 
 
 class MlpCfg(C.Structure):

@@ -180,6 +180,17 @@ def test_mech19_full_size_sampled(ctx, m19):
         eps = 2.0 ** -52 if prec == stev.F64 else 2.0 ** -24
         tol_sum = np.maximum(1e-12 if prec == stev.F64 else 2e-5, 4 * eps * g["iters"])
         assert np.all(np.abs(g["Y"].sum(axis=1) - 1.0) < tol_sum)
+        # the Sec 2.4 load histogram is the histogram of the per-cell counts,
+        # and the integration launch lies inside the call's timed span
+        st = g["stats"]
+        edges = np.asarray(stev.load_bin_edges() + [2 ** 34])
+        want = np.histogram(g["iters"], bins=edges)[0]
+        assert np.array_equal(np.asarray(st["load_hist"]), want)
+        curve = stev.load_curve(st["load_hist"])
+        assert curve[0][1] == len(T)    # every cell takes its first step
+        assert 0 < st["launch_ms"] <= st["kernel_ms"]
+        say(f"  load: {curve[:3]} ... {curve[-2:]}; launch {st['launch_ms']:.2f} of "
+            f"{st['kernel_ms']:.2f} ms")
         idx = synth.subsample(len(T), 96, seed=77 + prec)
         o = oracle_ensemble(om, T[idx], P[idx], Y[idx], DT, prec)
         gs = {k: (v[idx] if isinstance(v, np.ndarray) else v) for k, v in g.items()}

@@ -191,3 +191,71 @@ def test_failed_cells_and_tickets(ctx, mechs):
     with pytest.raises(stev.StevError) as e:
         ctx.submit(mechs[6][1], good["T"][:0], good["P"][:0], good["Y"][:0], DT)
     assert e.value.code == stev.STEV_EINVAL
+
+
+def test_concurrent_submit_and_poll(mechs):
+    """Eight threads submit and poll at once on a fresh context, so that the
+    first submits also race to create the serving state: every ticket
+    completes, each thread sees only its own tickets, and every result is
+    bit for bit that of stev_integrate on the same cells.  The threads stop
+    at the first failure any of them meets."""
+    import threading
+    c = stev.Context(0)
+    try:
+        m6 = c.mechanism(mechs[6][0])
+        prm = stev.default_params(precision=stev.F64)
+        n_thr, per_thr = 8, 12
+        rng = np.random.default_rng(107)
+        work = [[host_req(6, *cells(6, int(rng.integers(1, 400)), 1000 * t + i), np.float64)
+                 for i in range(per_thr)] for t in range(n_thr)]
+        for reqs in work:
+            for r in reqs:
+                r["T0"], r["Y0"] = r["T"].copy(), r["Y"].copy()
+        failed = threading.Event()
+        errors = []
+        start = threading.Barrier(n_thr)
+
+        def client(reqs):
+            try:
+                start.wait(timeout=60)
+                tks = []
+                for r in reqs:
+                    if failed.is_set():
+                        return
+                    tks.append(c.submit(m6, r["T"], r["P"], r["Y"], DT, params=prm,
+                                        iters=r["it"], status=r["st"]))
+                pending = set(tks)
+                t0 = time.time()
+                while pending and not failed.is_set():
+                    for tk in list(pending):
+                        rc, st = c.poll(tk)
+                        if rc == stev.STEV_EAGAIN:
+                            continue
+                        if rc != stev.STEV_OK:
+                            raise AssertionError(f"ticket {tk}: rc {rc}")
+                        pending.discard(tk)
+                    if time.time() - t0 > 120:
+                        raise AssertionError("requests did not finish")
+                    time.sleep(1e-4)
+            except BaseException as e:   # noqa: BLE001 -- reported below
+                errors.append(repr(e))
+                failed.set()
+
+        thr = [threading.Thread(target=client, args=(w,)) for w in work]
+        for t in thr:
+            t.start()
+        for t in thr:
+            t.join(timeout=180)
+        assert not any(t.is_alive() for t in thr), "client threads hung"
+        assert not errors, errors[:3]
+        for t, reqs in enumerate(work):
+            for i, r in enumerate(reqs):
+                T, Y = r["T0"].copy(), r["Y0"].copy()
+                it = np.zeros(len(T), np.int32)
+                c.integrate(m6, T, r["P"], Y, DT, params=prm, iters=it)
+                assert np.array_equal(T, r["T"]) and np.array_equal(Y, r["Y"]), (t, i)
+                assert np.array_equal(it, r["it"]) and not r["st"].any(), (t, i)
+        say(f"concurrent serving: {n_thr} threads x {per_thr} requests, all bit-identical")
+        m6.close()
+    finally:
+        c.close()

@@ -168,6 +168,32 @@ int stev_integrate(stev_ctx *ctx, const stev_mech *mech, int64_t n_cells,
                    int64_t ld_species, double dt_flow, const stev_params *params,
                    int32_t *iters_out, uint8_t *status_out, stev_stats *stats);
 
+/* stev_integrate for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, hosts that forbid hipMalloc during
+ * a run.  Same arguments, results (bit for bit), statistics and errors as
+ * stev_integrate, with three differences:
+ *  - T, P, Y and the non-NULL iters_out / status_out must be device
+ *    pointers (host arrays are refused with STEV_EINVAL: staging them would
+ *    allocate);
+ *  - n_cells <= stev_noalloc_max_cells() (4194304), else STEV_EINVAL;
+ *  - the call's work buffers (control words, the hottest-first dispatch
+ *    order, the probe's cell copies) live in a file-scope device array of
+ *    26 218 496 bytes (25 MiB) that every GPU the library runs on holds
+ *    until the process ends; nothing is allocated or freed and the context's HBM
+ *    budget is not charged.
+ * Calls made through one context are serialised, but every context on the
+ * same GPU shares that GPU's array: calls through different contexts on one
+ * GPU that overlap in time race on it and must not be made.  The array keeps
+ * the last call's contents; each call clears what it needs with a fill
+ * kernel (no hipMemsetAsync).  The mechanism (and any thermo network) must
+ * have been created beforehand. */
+int stev_integrate_noalloc(stev_ctx *ctx, const stev_mech *mech, int64_t n_cells, void *T,
+                           const void *P, void *Y, int64_t ld_cell, int64_t ld_species,
+                           double dt_flow, const stev_params *params, int32_t *iters_out,
+                           uint8_t *status_out, stev_stats *stats);
+/* Largest n_cells stev_integrate_noalloc accepts. */
+int64_t stev_noalloc_max_cells(void);
+
 /* Many independent cell batches (Sec 2.4 variable loading over all of them):
  * one persistent launch per distinct mechanism, whose global cell counter
  * runs over the concatenation of that mechanism's batches, so uneven batch

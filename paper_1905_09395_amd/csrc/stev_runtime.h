@@ -151,6 +151,8 @@ struct stev_ctx {
   // and published only once its scheduler runs; read without the lock
   std::mutex serve_mu;
   std::atomic<ServeState *> serve{nullptr};
+  // this device's copy of the allocation-free entry point's scratch array
+  void *noalloc_scratch = nullptr;
   std::map<std::string, stev_params> tune_cache;
   // multi-batch launches: side streams for mechanism groups, fork/join events
   // and the cache of recorded launch sequences (HIP graphs), keyed by call
@@ -218,6 +220,10 @@ int finish_field(stev_ctx *ctx, const LaunchPlan &lp, long long n_cells,
 // thermo network (stev_mlp.hip)
 void mlp_release(stev_ctx *ctx, stev_mech *m);
 int mlp_wave_bytes(const stev_mech *m, const stev_params &p, int G);
+
+// allocation-free entry point (stev_noalloc.hip): device address of the
+// scratch array, looked up once per device with that device current
+int noalloc_setup(stev_ctx *ctx);
 
 // serving (stev_serve.hip)
 void serve_stop(stev_ctx *ctx);

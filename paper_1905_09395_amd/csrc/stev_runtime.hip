@@ -171,6 +171,10 @@ extern "C" int stev_init(stev_ctx **out, int hip_device, size_t hbm_budget_bytes
     stev_shutdown(ctx);
     return STEV_EDEVICE;
   }
+  if (noalloc_setup(ctx) != STEV_OK) {
+    stev_shutdown(ctx);
+    return STEV_EDEVICE;
+  }
   *out = ctx;
   return STEV_OK;
 }

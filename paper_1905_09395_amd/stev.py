@@ -153,6 +153,10 @@ def load():
     L.stev_create_mechanism.argtypes = [vp, C.POINTER(MechDesc), C.POINTER(vp)]
     L.stev_integrate.argtypes = [vp, vp, i64, vp, vp, vp, i64, i64, dbl, C.POINTER(Params),
                                  vp, vp, C.POINTER(Stats)]
+    L.stev_integrate_noalloc.argtypes = [vp, vp, i64, vp, vp, vp, i64, i64, dbl,
+                                         C.POINTER(Params), vp, vp, C.POINTER(Stats)]
+    L.stev_noalloc_max_cells.argtypes = []
+    L.stev_noalloc_max_cells.restype = i64
     L.stev_integrate_batched.argtypes = [vp, i32, C.POINTER(vp), C.POINTER(i64), C.POINTER(vp),
                                          C.POINTER(vp), C.POINTER(vp), C.POINTER(i64),
                                          C.POINTER(i64), dbl, C.POINTER(Params), C.POINTER(vp),
@@ -310,6 +314,28 @@ class Context:
                                      float(dt_flow), C.byref(params), pI, pS, C.byref(st))
         self._check(rc, (STEV_OK, STEV_ECELLS) if allow_failed else (STEV_OK,))
         return rc, st.as_dict()
+
+    def integrate_noalloc(self, mech, T, P, Y, dt_flow, params=None, iters=None, status=None,
+                          ld_cell=None, ld_species=None, allow_failed=False):
+        """stev_integrate_noalloc: as integrate(), device tensors only; the
+        library allocates nothing during the call."""
+        params = params or default_params()
+        n = int(T.shape[0])
+        if ld_cell is None:
+            ld_cell = int(Y.shape[1]) if len(Y.shape) == 2 else mech.n_s
+        if ld_species is None:
+            ld_species = 1
+        _after_torch()
+        st = Stats()
+        rc = self.lib.stev_integrate_noalloc(self.h, mech.h, n, _ptr(T)[0], _ptr(P)[0],
+                                             _ptr(Y)[0], int(ld_cell), int(ld_species),
+                                             float(dt_flow), C.byref(params), _ptr(iters)[0],
+                                             _ptr(status)[0], C.byref(st))
+        self._check(rc, (STEV_OK, STEV_ECELLS) if allow_failed else (STEV_OK,))
+        return rc, st.as_dict()
+
+    def noalloc_max_cells(self):
+        return int(self.lib.stev_noalloc_max_cells())
 
     def integrate_batched(self, mechs, Ts, Ps, Ys, dt_flow, params=None, iters=None,
                           status=None, allow_failed=False):

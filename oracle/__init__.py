@@ -17,6 +17,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "stev_oracle.c")
+_SRC_C3M = os.path.join(_HERE, "c3m_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 # a mutated build of the same sources (tests/test_oracle_mutations.py) is
 # loaded in a child process through this variable; nothing else sets it
@@ -28,7 +29,7 @@ def build(force=True):
     """Compile the oracle with gcc (FP64, no FMA contraction, OpenMP)."""
     cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math",
            "-fopenmp", "-fPIC", "-shared", "-Wall", "-Wextra", "-o", _LIB + ".tmp",
-           _SRC, "-lm"]
+           _SRC, _SRC_C3M, "-lm"]
     if force or not os.path.exists(_LIB):
         subprocess.check_call(cmd, cwd=_HERE)
         os.replace(_LIB + ".tmp", _LIB)
@@ -55,6 +56,46 @@ class _Params(C.Structure):
 DEFAULT_PARAMS = dict(ystep_max=1e-3, delta_max=1e-2, alpha=1e-5, tol_ring=0.5,
                       tol_freq=1e-6, r_fac=2.0, rof_min=1e-12, dft_window=13,
                       stab_limit=0, max_iters=1_000_000, noise_eps=0.0, noise_seed=0)
+
+
+C3M_NG, C3M_NS, C3M_NR, C3M_NVAR = 14, 4, 11, 26
+C3M_GAS = ("CO", "CO2", "CH4", "H2", "H2O", "H2S", "C3H6", "HCN", "C2H4", "C2H6", "Tar", "O2",
+           "SO3", "N2")
+C3M_SOLID = ("CV", "CC", "CM", "CA")
+C3M_REACTIONS = ("PYRO", "WGS", "STG", "CG", "MEG", "COX", "TOX", "COOX", "HOX", "MEOX", "MR")
+C3M_VARS = ("T_g", "T_s", "P_g", "ep_g", "rho_g", "ep_s", "rho_s", "d_p")
+
+
+class _C3M(C.Structure):
+    _fields_ = [("A_pyro", C.c_double), ("Ea_pyro", C.c_double),
+                ("A_wgs", C.c_double), ("Fp_wgs", C.c_double), ("Kf_wgs", C.c_double),
+                ("Eaf_wgs", C.c_double), ("Kr_wgs", C.c_double), ("Ear_wgs", C.c_double),
+                ("theta_G", C.c_double * 5), ("theta_C", C.c_double * 5),
+                ("A_stg", C.c_double), ("Fp_stg", C.c_double), ("Ea_stg", C.c_double),
+                ("A_cg", C.c_double), ("Fp_cg", C.c_double), ("Ea_cg", C.c_double),
+                ("A_meg", C.c_double), ("Ea_meg", C.c_double), ("beta_c", C.c_double),
+                ("A_cox", C.c_double), ("Ea_cox", C.c_double),
+                ("A_tox", C.c_double), ("Ea_tox", C.c_double),
+                ("A_coox", C.c_double), ("Ea_coox", C.c_double),
+                ("A_hox", C.c_double), ("Ea_hox", C.c_double),
+                ("A_meox", C.c_double), ("Ea_meox", C.c_double), ("A_mr", C.c_double),
+                ("nu_pyro", C.c_double * 11), ("nu_tox", C.c_double * 5),
+                ("W_g", C.c_double * 14), ("W_s", C.c_double * 4)]
+
+
+class C3M:
+    """C view of a C3M description (a dict as made by synth.make_c3m)."""
+
+    def __init__(self, desc):
+        self.desc = desc
+        c = _C3M()
+        for f, t in _C3M._fields_:
+            v = desc[f]
+            if hasattr(t, "_length_"):
+                getattr(c, f)[:] = [float(x) for x in v]
+            else:
+                setattr(c, f, float(v))
+        self.c = c
 
 
 def lib():
@@ -98,6 +139,18 @@ def lib():
         L.orc_mlp_loss_grad.restype = C.c_double
         L.orc_adam_step.argtypes = [C.c_longlong, dp, dp, dp, dp, C.c_longlong, C.c_double,
                                     C.c_double, C.c_double, C.c_double]
+        L.orc_c3m_anneal.argtypes = [C.POINTER(_C3M), C.c_double, C.c_double, dp, dp, dp]
+        L.orc_c3m_rates.argtypes = [C.POINTER(_C3M), C.POINTER(_Params), dp, C.c_double,
+                                    C.c_double, dp, dp, dp]
+        L.orc_c3m_source.argtypes = [C.POINTER(_C3M), C.POINTER(_Params), dp, C.c_double,
+                                     C.c_double, dp, dp, C.c_double, dp, dp, dp, dp, dp, dp]
+        L.orc_c3m_integrate_cell.argtypes = [C.POINTER(_C3M), C.POINTER(_Params), dp,
+                                             C.c_double, C.POINTER(C.c_longlong)]
+        L.orc_c3m_integrate_cell.restype = C.c_int
+        L.orc_c3m_integrate.argtypes = [C.POINTER(_C3M), C.POINTER(_Params), C.c_longlong, dp,
+                                        C.c_longlong, C.c_double, C.POINTER(C.c_longlong),
+                                        C.POINTER(C.c_ubyte), C.c_int]
+        L.orc_c3m_integrate.restype = C.c_int
         _lib = L
     return _lib
 
@@ -275,3 +328,58 @@ def adam_step(prm, grad, m1, m2, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8
     """In-place Adam update of prm, m1, m2 (float64 arrays)."""
     lib().orc_adam_step(len(prm), _p(prm), _p(np.ascontiguousarray(grad)), _p(m1), _p(m2),
                         int(step), lr, beta1, beta2, eps)
+
+
+def c3m_anneal(c3, X_CC, X_CA):
+    """Eqs 44-46: (vartheta, alpha_G, alpha_C)."""
+    th, aG, aC = C.c_double(), C.c_double(), C.c_double()
+    lib().orc_c3m_anneal(C.byref(c3.c), float(X_CC), float(X_CA), C.byref(th), C.byref(aG),
+                         C.byref(aC))
+    return th.value, aG.value, aC.value
+
+
+def _c3m_split(cell, ROP_g=None, ROP_s=None):
+    cell = np.ascontiguousarray(cell, dtype=np.float64)
+    ROP_g = cell[3] * cell[4] if ROP_g is None else ROP_g
+    ROP_s = cell[5] * cell[6] if ROP_s is None else ROP_s
+    Xg = np.ascontiguousarray(cell[8:22])
+    Xs = np.ascontiguousarray(cell[22:26])
+    return cell, float(ROP_g), float(ROP_s), Xg, Xs
+
+
+def c3m_rates(c3, cell, ROP_g=None, ROP_s=None, **kw):
+    """Eqs 42-56 at one 26-value cell state: r[11] (kmol/m^3/s)."""
+    prm = make_params(**kw)
+    cell, Rg, Rs, Xg, Xs = _c3m_split(cell, ROP_g, ROP_s)
+    r = np.zeros(C3M_NR)
+    lib().orc_c3m_rates(C.byref(c3.c), C.byref(prm), _p(cell), Rg, Rs, _p(Xg), _p(Xs), _p(r))
+    return r
+
+
+def c3m_source(c3, cell, rof=1.0, ROP_g=None, ROP_s=None, **kw):
+    """dict(r, dXg, dXs, dROPg, dROPs, src) at one cell state (src: the
+    species mass sources W_k omega_k, gas then solids)."""
+    prm = make_params(**kw)
+    cell, Rg, Rs, Xg, Xs = _c3m_split(cell, ROP_g, ROP_s)
+    r = np.zeros(C3M_NR)
+    dXg = np.zeros(C3M_NG)
+    dXs = np.zeros(C3M_NS)
+    dRg = np.zeros(1)
+    dRs = np.zeros(1)
+    src = np.zeros(C3M_NG + C3M_NS)
+    lib().orc_c3m_source(C.byref(c3.c), C.byref(prm), _p(cell), Rg, Rs, _p(Xg), _p(Xs),
+                         float(rof), _p(r), _p(dXg), _p(dXs), _p(dRg), _p(dRs), _p(src))
+    return dict(r=r, dXg=dXg, dXs=dXs, dROPg=float(dRg[0]), dROPs=float(dRs[0]), src=src)
+
+
+def c3m_integrate(c3, state, tf, nthreads=0, **kw):
+    """Integrate cells [n, 26] over tf; returns dict(state, iters, status)."""
+    prm = make_params(**kw)
+    st = np.array(state, dtype=np.float64).copy()
+    n = st.shape[0]
+    iters = np.zeros(n, dtype=np.int64)
+    status = np.zeros(n, dtype=np.uint8)
+    lib().orc_c3m_integrate(C.byref(c3.c), C.byref(prm), n, _p(st), st.shape[1], float(tf),
+                            iters.ctypes.data_as(C.POINTER(C.c_longlong)),
+                            status.ctypes.data_as(C.POINTER(C.c_ubyte)), int(nthreads))
+    return dict(state=st, iters=iters, status=status)

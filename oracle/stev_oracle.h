@@ -126,6 +126,93 @@ void orc_adam_step(long long n_prm, double *prm, const double *grad, double *m1,
                    double *m2, long long step, double lr, double beta1,
                    double beta2, double eps);
 
+/* ---------------------------------------------------------------------------
+ * Multiphase coal gasification chemistry (Sec 7.2): the C3M reactions of
+ * Eqs 31-41 with the rate laws of Eqs 42-56 and the constants of Table 2,
+ * integrated by the same STEV steps (Eqs 1-14) over one flow step.
+ *
+ * Species order.  Gas (14): CO CO2 CH4 H2 H2O H2S C3H6 HCN C2H4 C2H6 Tar O2
+ * SO3 N2.  Solid (4): CV (volatile matter) CC (fixed carbon) CM (moisture,
+ * H2O(s)) CA (ash).  Reactions (11): PYRO WGS STG CG MEG COX TOX COOX HOX
+ * MEOX MR (Eqs 31-41, in the paper's order).
+ *
+ * Cell state, 26 values: T_g, T_s, P_g, ep_g, rho_g, ep_s, rho_s, d_p,
+ * X_g[14], X_s[4].  Units are MFiX SI: K, Pa, kg/m^3, m; rates in
+ * kmol/(m^3 s); molar masses in kg/kmol; Table 2's Ea are temperatures (K).
+ *
+ * Readings (the paper gives the rate laws only):
+ *  - the chemistry step is isothermal and isobaric in each phase: T_g, T_s
+ *    and P_g stay as the flow solver handed them over, as do rho_s (the
+ *    solid material density) and d_p;
+ *  - the phase bulk densities ROP_g = ep_g rho_g and ROP_s = ep_s rho_s
+ *    change by the interphase mass transfer of the reactions; ep_s = ROP_s /
+ *    rho_s, and the volume the solids give up goes to the gas:
+ *    ep_g = (ep_g0 + ep_s0) - ep_s, rho_g = ROP_g / ep_g;
+ *  - species equations per phase in conservative form: the species
+ *    masses m_k = ROP X_k (kg/m^3) advance by forward Euler (Eq 18),
+ *    m_k += h W_k omega_k, and ROP = sum m_k, X_k = m_k / ROP follow, so
+ *    that phase transfer conserves every species' and element's mass
+ *    exactly; Eqs 1-3 use the mass fractions and their rates
+ *    dX_k/dt = (W_k omega_k - X_k dROP/dt) / ROP;
+ *  - inside the rate laws every X is max(X, 0) and gamma (Eq 7) acts on it;
+ *    Eq 44 uses the raw fractions (its clamps are there for negatives);
+ *  - Eq 46 as printed: theta_1 multiplies vartheta, the other terms phi;
+ *  - partial pressures MW_g P_g X_k / W_k use the molar masses printed in
+ *    Eqs 47-50 and the mixture molar mass from the raw gas fractions;
+ *  - STEV's step rule (Eqs 1-5) runs over all 18 mass fractions; the DFT
+ *    ring (Eqs 8-14) over the one reversible reaction, WGS; Tol_freq is
+ *    given in mol/m^3 like everywhere else and compared in kmol/m^3. */
+#define ORC_C3M_NG 14
+#define ORC_C3M_NS 4
+#define ORC_C3M_NR 11
+#define ORC_C3M_NVAR 26
+
+typedef struct {
+  double A_pyro, Ea_pyro;
+  double A_wgs, Fp_wgs, Kf_wgs, Eaf_wgs, Kr_wgs, Ear_wgs;
+  double theta_G[5];   /* theta_0 .. theta_4, gasification */
+  double theta_C[5];   /* theta_0 .. theta_4, char combustion */
+  double A_stg, Fp_stg, Ea_stg;
+  double A_cg, Fp_cg, Ea_cg;
+  double A_meg, Ea_meg;
+  double beta_c;
+  double A_cox, Ea_cox;
+  double A_tox, Ea_tox;
+  double A_coox, Ea_coox;
+  double A_hox, Ea_hox;
+  double A_meox, Ea_meox;
+  double A_mr;
+  double nu_pyro[11];  /* Eq 31: kmol of CO .. Tar (gas order 0..10) per kmol CV */
+  double nu_tox[5];    /* Eq 37: O2 (negative), CO2, H2O, SO3, N2 per kmol Tar */
+  double W_g[ORC_C3M_NG], W_s[ORC_C3M_NS];   /* kg/kmol */
+} orc_c3m;
+
+/* Eqs 44-46: reaction progress and the two annealing factors. */
+void orc_c3m_anneal(const orc_c3m *c, double X_CC, double X_CA, double *vartheta,
+                    double *alpha_G, double *alpha_C);
+
+/* Eqs 42-56 for one cell state (26 values), with the phase bulk densities
+ * ROP_g, ROP_s in place of ep/rho (see the readings above): r[11]. */
+void orc_c3m_rates(const orc_c3m *c, const orc_params *p, const double *cell, double ROP_g,
+                   double ROP_s, const double *X_g, const double *X_s, double r[ORC_C3M_NR]);
+
+/* Species and phase-mass rates with WGS damped by rof (Eq 14): r (undamped),
+ * dX_g[14], dX_s[4], dROP_g, dROP_s, and (nullable) src[18], the species
+ * mass sources W_k omega_k in kg/(m^3 s), gas then solids. */
+void orc_c3m_source(const orc_c3m *c, const orc_params *p, const double *cell, double ROP_g,
+                    double ROP_s, const double *X_g, const double *X_s, double rof,
+                    double r[ORC_C3M_NR], double *dX_g, double *dX_s, double *dROP_g,
+                    double *dROP_s, double *src);
+
+/* One cell over [0, tf], in place on its 26 values.  Status as orc_integrate_cell. */
+int orc_c3m_integrate_cell(const orc_c3m *c, const orc_params *p, double *cell, double tf,
+                           long long *iters);
+
+/* All cells: state[c * ld + v]; optional outputs may be NULL. */
+int orc_c3m_integrate(const orc_c3m *c, const orc_params *p, long long n, double *state,
+                      long long ld, double tf, long long *iters, unsigned char *status,
+                      int nthreads);
+
 #ifdef __cplusplus
 }
 #endif

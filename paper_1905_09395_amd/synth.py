@@ -36,7 +36,9 @@ exothermic at 298 K, so that reverse barriers are never negative.
 from __future__ import annotations
 
 import itertools
+import json
 import math
+import os
 
 import numpy as np
 from numpy.polynomial import Polynomial
@@ -429,3 +431,112 @@ def make_batches(n_batches=64, lo=256, hi=131072, seed=103):
         else:
             out.append((19,) + make_cells_mech19(int(n), seed=s))
     return out
+
+
+# ---------------------------------------------------------------------------
+# Multiphase coal gasification (Sec 7.2): the C3M description and cell fields
+# ---------------------------------------------------------------------------
+C3M_GAS = ("CO", "CO2", "CH4", "H2", "H2O", "H2S", "C3H6", "HCN", "C2H4", "C2H6", "Tar", "O2",
+           "SO3", "N2")
+C3M_SOLID = ("CV", "CC", "CM", "CA")
+# element masses (kg/kmol) whose sums give the molar masses printed in
+# Eqs 47-50 to their printed digits
+ELEMENT_MASS = {"C": 12.011, "H": 1.00794, "O": 15.9994, "N": 14.0067, "S": 32.065}
+C3M_FORMULA = {"CO": {"C": 1, "O": 1}, "CO2": {"C": 1, "O": 2}, "CH4": {"C": 1, "H": 4},
+               "H2": {"H": 2}, "H2O": {"H": 2, "O": 1}, "H2S": {"H": 2, "S": 1},
+               "C3H6": {"C": 3, "H": 6}, "HCN": {"H": 1, "C": 1, "N": 1},
+               "C2H4": {"C": 2, "H": 4}, "C2H6": {"C": 2, "H": 6}, "O2": {"O": 2},
+               "SO3": {"S": 1, "O": 3}, "N2": {"N": 2}}
+# ash takes part in no reaction; its molar mass (silica's) only labels it
+ASH_MOLAR_MASS = 60.0843
+C3M_TABLE2 = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                          "tests", "golden", "c3m_table2.json")
+
+
+def _formula_mass(f):
+    return sum(ELEMENT_MASS[e] * n for e, n in f.items())
+
+
+def c3m_compositions(desc):
+    """Element content (kmol per kmol) of every species, the pseudo-species
+    included: tar from the atom balance of Eq 37, volatile matter from that
+    of Eq 31, fixed carbon C, moisture H2O, ash none."""
+    comp = {k: dict(C3M_FORMULA[k]) for k in C3M_FORMULA}
+    nt = dict(zip(("O2", "CO2", "H2O", "SO3", "N2"), desc["nu_tox"]))
+    tar = {}
+    for sp, n in nt.items():
+        for e, a in C3M_FORMULA[sp].items():
+            tar[e] = tar.get(e, 0.0) + n * a
+    comp["Tar"] = tar
+    cv = {}
+    for sp, n in zip(C3M_GAS[:11], desc["nu_pyro"]):
+        for e, a in comp[sp].items():
+            cv[e] = cv.get(e, 0.0) + n * a
+    comp["CV"] = cv
+    comp["CC"] = {"C": 1}
+    comp["CM"] = {"H": 2, "O": 1}
+    comp["CA"] = {}
+    return comp
+
+
+def make_c3m(table2_path=C3M_TABLE2):
+    """The C3M gasification chemistry with the paper's constants (Table 2,
+    Eqs 31 and 37).  Molar masses follow from the element masses; those of
+    the pseudo-species tar and volatile matter from the atom balances of
+    Eqs 37 and 31, so every reaction conserves mass exactly."""
+    with open(table2_path) as f:
+        g = json.load(f)
+    t = g["table2"]
+    desc = dict(A_pyro=t["A_PYRO"], Ea_pyro=t["Ea_PYRO"],
+                A_wgs=t["A_WGS"], Fp_wgs=t["F_P_WGS"], Kf_wgs=t["K_F_WGS"],
+                Eaf_wgs=t["Ea_F_WGS"], Kr_wgs=t["K_R_WGS"], Ear_wgs=t["Ea_R_WGS"],
+                theta_G=[t[f"theta{i}_G"] for i in range(5)],
+                theta_C=[t[f"theta{i}_C"] for i in range(5)],
+                A_stg=t["A_STG"], Fp_stg=t["F_P_STG"], Ea_stg=t["Ea_STG"],
+                A_cg=t["A_CG"], Fp_cg=t["F_P_CG"], Ea_cg=t["Ea_CG"],
+                A_meg=t["A_MEG"], Ea_meg=t["Ea_MEG"], beta_c=t["beta_c"],
+                A_cox=t["A_COX"], Ea_cox=t["Ea_COX"], A_tox=t["A_TOX"], Ea_tox=t["Ea_TOX"],
+                A_coox=t["A_COOX"], Ea_coox=t["Ea_COOX"], A_hox=t["A_HOX"], Ea_hox=t["Ea_HOX"],
+                A_meox=t["A_MEOX"], Ea_meox=t["Ea_MEOX"], A_mr=t["A_MR"])
+    py = g["eq31_pyrolysis_products_per_CV"]
+    desc["nu_pyro"] = [py[k] for k in C3M_GAS[:11]]
+    tx = g["eq37_tar_oxidation_per_Tar"]
+    desc["nu_tox"] = [tx[k] for k in ("O2", "CO2", "H2O", "SO3", "N2")]
+    comp = c3m_compositions(desc)
+    W = {k: _formula_mass(comp[k]) for k in C3M_GAS}
+    desc["W_g"] = [W[k] for k in C3M_GAS]
+    desc["W_s"] = [_formula_mass(comp["CV"]), ELEMENT_MASS["C"], W["H2O"], ASH_MOLAR_MASS]
+    return desc
+
+
+R_KMOL = 8314.46261815324   # J/(kmol K)
+
+
+def make_c3m_cells(n=262144, seed=108, desc=None):
+    """Random gasifier states, 26 values per cell (T_g, T_s, P_g, ep_g, rho_g,
+    ep_s, rho_s, d_p, X_g[14], X_s[4]; K, Pa, kg/m^3, m):
+    T_g ~ U[900, 1400] K, T_s = T_g + U[-50, 50] K, P_g ~ U[1, 15] atm,
+    ep_s ~ U[0.02, 0.3], ep_g = 1 - ep_s, rho_s ~ U[900, 1400] kg/m^3,
+    d_p log-uniform in [50, 500] um, X_g ~ Dirichlet(1) over the 14 gas
+    species, X_s = 0.1 ash + 0.9 Dirichlet(1) over the 4 solids, and rho_g
+    from the ideal gas at T_g, P_g."""
+    desc = desc or make_c3m()
+    rng = np.random.default_rng(seed)
+    st = np.zeros((n, 26))
+    Tg = rng.uniform(900.0, 1400.0, n)
+    st[:, 0] = Tg
+    st[:, 1] = Tg + rng.uniform(-50.0, 50.0, n)
+    st[:, 2] = rng.uniform(1.0, 15.0, n) * 101325.0
+    eps = rng.uniform(0.02, 0.3, n)
+    st[:, 5] = eps
+    st[:, 3] = 1.0 - eps
+    st[:, 6] = rng.uniform(900.0, 1400.0, n)
+    st[:, 7] = np.exp(rng.uniform(np.log(50e-6), np.log(500e-6), n))
+    Xg = rng.dirichlet(np.ones(14), n)
+    Xs = 0.9 * rng.dirichlet(np.ones(4), n)
+    Xs[:, 3] += 0.1
+    st[:, 8:22] = Xg
+    st[:, 22:26] = Xs
+    mw = 1.0 / (Xg / np.asarray(desc["W_g"])).sum(axis=1)
+    st[:, 4] = st[:, 2] * mw / (R_KMOL * Tg)
+    return st

@@ -57,14 +57,67 @@ MUTATIONS = [
 ]
 
 
-def _build(src_text, out_dir):
+SRC_C3M = os.path.join(ROOT, "oracle", "c3m_oracle.c")
+
+# the same for the multiphase oracle, caught by tests/test_oracle_c3m.py
+C3M_MUTATIONS = [
+    # Eq 42 evaluated at the gas temperature
+    ("pyro_at_gas_temperature",
+     "exp(-c->Ea_pyro / T_s);",
+     "exp(-c->Ea_pyro / T_g);",
+     "arrhenius and PYRO"),
+    # Eq 46: theta_1 on phi instead of vartheta
+    ("anneal_theta1_on_phi",
+     "g[1] * th + g[0];",
+     "g[1] * phi + g[0];",
+     "anneal"),
+    # Eq 54 without its gamma(X_H2)
+    ("hox_gamma_dropped",
+     "pos(X_g[G_H2]) * gam(X_g[G_O2], a) * gam(X_g[G_H2], a);",
+     "pos(X_g[G_H2]) * gam(X_g[G_O2], a);",
+     "gamma_factor_of_gas"),
+    # Eq 51: film temperature weighted to the gas
+    ("film_temperature_skewed",
+     "const double T_film = 0.5 * T_g + 0.5 * T_s;",
+     "const double T_film = 0.75 * T_g + 0.25 * T_s;",
+     "arrhenius and COX"),
+    # Eqs 1-3 over the gas fractions only
+    ("step_rule_gas_only",
+     "double h = orc_step_size(p, NX, X, dX, t, tf);",
+     "double h = orc_step_size(p, NG, X, dX, t, tf);",
+     "step_rule"),
+    # Eq 38: half the oxygen of CO oxidation dropped
+    ("coox_oxygen_dropped",
+     "nu[R_COOX][G_O2] = -0.5;",
+     "nu[R_COOX][G_O2] = -1.0;",
+     "conserved"),
+    # Eq 14 damping applied to a reaction that has no ring
+    ("damping_on_hox",
+     "double r_eff = (j == R_WGS) ? rof * r[j] : r[j];",
+     "double r_eff = (j == R_WGS || j == R_HOX) ? rof * r[j] : r[j];",
+     "damping_applies"),
+    # solids volume fraction taken as the bulk density
+    ("eps_s_not_divided",
+     "const double ep_s = ROP_s / rho_s;\n  const double ep_g",
+     "const double ep_s = ROP_s;\n  const double ep_g",
+     "solid_geometry"),
+]
+
+
+def _build(src_text, out_dir, c3m_text=None):
     c = os.path.join(out_dir, "stev_oracle.c")
     with open(c, "w") as f:
         f.write(src_text)
+    if c3m_text is not None:
+        with open(os.path.join(out_dir, "c3m_oracle.c"), "w") as f:
+            f.write(c3m_text)
     shutil.copy(os.path.join(ROOT, "oracle", "stev_oracle.h"), out_dir)
+    c3m = os.path.join(out_dir, "c3m_oracle.c")
+    if not os.path.exists(c3m):
+        shutil.copy(os.path.join(ROOT, "oracle", "c3m_oracle.c"), out_dir)
     lib = os.path.join(out_dir, "liboracle_mut.so")
     subprocess.check_call(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math",
-                           "-fopenmp", "-fPIC", "-shared", "-o", lib, c, "-lm"])
+                           "-fopenmp", "-fPIC", "-shared", "-o", lib, c, c3m, "-lm"])
     return lib
 
 
@@ -77,6 +130,22 @@ def test_pins_catch_planted_mistake(tmp_path, name, old, new, pins):
     env = dict(os.environ, STEV_ORACLE_LIB=lib)
     r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider",
                         os.path.join(ROOT, "tests", "test_oracle_pins.py"), "-k", pins],
+                       cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
+    assert r.returncode == 1 and "failed" in r.stdout, (
+        f"pins '{pins}' did not catch {name}:\n{r.stdout[-2000:]}")
+
+
+@pytest.mark.parametrize("name,old,new,pins", C3M_MUTATIONS, ids=[m[0] for m in C3M_MUTATIONS])
+def test_c3m_pins_catch_planted_mistake(tmp_path, name, old, new, pins):
+    with open(SRC_C3M) as f:
+        text = f.read()
+    assert text.count(old) == 1, f"mutation site for {name} not unique/found"
+    with open(SRC) as f:
+        base = f.read()
+    lib = _build(base, str(tmp_path), text.replace(old, new))
+    env = dict(os.environ, STEV_ORACLE_LIB=lib)
+    r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider",
+                        os.path.join(ROOT, "tests", "test_oracle_c3m.py"), "-k", pins],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
     assert r.returncode == 1 and "failed" in r.stdout, (
         f"pins '{pins}' did not catch {name}:\n{r.stdout[-2000:]}")

@@ -362,6 +362,74 @@ int stev_autotune(stev_ctx *ctx, const stev_mech *mech, int64_t n_cells, const v
                   const void *P, const void *Y, int64_t ld_cell, int64_t ld_species,
                   double dt_flow, stev_params *inout);
 
+/* ---------------------------------------------------------------------------
+ * Multiphase coal gasification (Sec 7.2): the C3M reactions of Eqs 31-41
+ * (pyrolysis of volatile matter, water-gas shift, steam, CO2 and H2
+ * gasification and oxidation of char, tar, CO, H2 and CH4 oxidation,
+ * moisture release) with the rate laws of Eqs 42-56, integrated by the
+ * same STEV steps: Eqs 1-5 over the 18 mass fractions of both phases,
+ * forward Euler on the species masses, DFT damping of the water-gas shift
+ * (the one reversible reaction), variable loading.
+ *
+ * Species: gas (14) CO CO2 CH4 H2 H2O H2S C3H6 HCN C2H4 C2H6 Tar O2 SO3 N2;
+ * solid (4) CV (volatile matter) CC (fixed carbon) CM (moisture) CA (ash).
+ * Units (MFiX SI): K, Pa, kg/m^3, m; rates in kmol/(m^3 s); molar masses in
+ * kg/kmol; Table 2's activation energies are temperatures (K). */
+typedef struct {
+  double A_pyro, Ea_pyro;                               /* Eq 42 */
+  double A_wgs, Fp_wgs, Kf_wgs, Eaf_wgs, Kr_wgs, Ear_wgs;  /* Eq 43 */
+  double theta_G[5];   /* Eq 46, gasification: theta_0 .. theta_4 */
+  double theta_C[5];   /* Eq 46, char combustion */
+  double A_stg, Fp_stg, Ea_stg;                         /* Eq 47 */
+  double A_cg, Fp_cg, Ea_cg;                            /* Eq 48 */
+  double A_meg, Ea_meg;                                 /* Eq 49 */
+  double beta_c;                                        /* Eq 44 */
+  double A_cox, Ea_cox;                                 /* Eq 50 */
+  double A_tox, Ea_tox;                                 /* Eq 52 */
+  double A_coox, Ea_coox;                               /* Eq 53 */
+  double A_hox, Ea_hox;                                 /* Eq 54 */
+  double A_meox, Ea_meox;                               /* Eq 55 */
+  double A_mr;                                          /* Eq 56 */
+  double nu_pyro[11];  /* Eq 31: kmol of CO, CO2, CH4, H2, H2O, H2S, C3H6, HCN,
+                          C2H4, C2H6, Tar per kmol of CV */
+  double nu_tox[5];    /* Eq 37: O2 (negative), CO2, H2O, SO3, N2 per kmol of Tar */
+  double W_g[14];      /* molar masses, gas order above, kg/kmol (> 0) */
+  double W_s[4];       /* molar masses, solid order above (> 0) */
+} stev_c3m_desc;
+typedef struct stev_c3m stev_c3m;
+
+/* Copy and validate a C3M description (every value finite, molar masses
+ * > 0); device-resident until destroyed.  The caller keeps ownership. */
+int stev_c3m_create(stev_ctx *ctx, const stev_c3m_desc *desc, stev_c3m **out);
+void stev_c3m_destroy(stev_ctx *ctx, stev_c3m *c3m);
+
+/* Integrate n_cells gas-solid cells over one flow step dt_flow, in place.
+ * Cell c's 26 values are state[c * ld_cell + v * ld_var], v in the order
+ * T_g, T_s, P_g, ep_g, rho_g, ep_s, rho_s, d_p, X_g[14], X_s[4] (double or
+ * float per params->precision; host or device pointer).  The chemistry step
+ * holds T_g, T_s, P_g, rho_s (solid material density) and d_p; it moves the
+ * mass fractions and, through the mass the reactions carry between the
+ * phases, the bulk densities ep_g rho_g and ep_s rho_s: ep_s = (ep_s rho_s)
+ * / rho_s, the volume the solids give up goes to the gas (ep_g + ep_s keeps
+ * its value), rho_g = (ep_g rho_g) / ep_g.  Written back: X_g, X_s, ep_g,
+ * rho_g, ep_s (a cell that takes no step keeps its 26 values).  params: precision, ystep_max, delta_max, alpha, tol_ring,
+ * tol_freq (mol/m^3, compared with the ring in kmol/m^3), r_fac, rof_min,
+ * dft_window, max_iters, waves_per_wg, compact_every, grid_wgs as for
+ * stev_integrate; thermo must be STEV_THERMO_POLY (no thermo is used),
+ * stab_limit 0 and lanes_per_cell 0 or 1 (one cell per lane), else
+ * STEV_EINVAL.  Cells run in array order.  iters_out / status_out
+ * optional; stats as for stev_integrate (load histogram and launch_ms
+ * included).  Blocking.  STEV_ECELLS if a cell failed (1 non-finite, 2
+ * max_iters; a failed cell keeps its last finite state). */
+int stev_c3m_integrate(stev_ctx *ctx, const stev_c3m *c3m, int64_t n_cells, void *state,
+                       int64_t ld_cell, int64_t ld_var, double dt_flow, const stev_params *params,
+                       int32_t *iters_out, uint8_t *status_out, stev_stats *stats);
+
+/* FLOPs of one C3M cell-iteration (add/mul = 1, FMA = 2, the WGS DFT as
+ * direct sums); *transc receives the logarithms, exponentials and square
+ * roots per iteration. */
+double stev_c3m_model_flops(double *transc);
+
 /* Model FLOPs of one cell-iteration for this mechanism (add/mul = 1,
  * FMA = 2; transcendentals counted separately in *transc). */
 double stev_model_flops(const stev_mech *mech, int32_t thermo, double *transc);

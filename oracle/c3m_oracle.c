@@ -29,6 +29,20 @@ enum { R_PYRO, R_WGS, R_STG, R_CG, R_MEG, R_COX, R_TOX, R_COOX, R_HOX, R_MEOX, R
 enum { V_TG, V_TS, V_PG, V_EPG, V_ROG, V_EPS, V_ROS, V_DP, V_XG };
 #define V_XS (V_XG + ORC_C3M_NG)
 
+/* splitmix64 (Steele, Lea & Flood 2014), used only by the noise instrument */
+static unsigned long long c3m_mix64(unsigned long long z) {
+  z += 0x9E3779B97F4A7C15ULL;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+  return z ^ (z >> 31);
+}
+
+/* uniform in [-1, 1) from (key, j) */
+static double c3m_noise_u(unsigned long long key, int j) {
+  unsigned long long r = c3m_mix64(key ^ c3m_mix64(0xC3E5ULL + (unsigned long long)j));
+  return (double)(r >> 11) * (1.0 / 4503599627370496.0) - 1.0;
+}
+
 /* Eq 7 on max(X, 0) */
 static double gam(double X, double alpha) {
   double x = X > 0.0 ? X : 0.0;
@@ -167,6 +181,10 @@ static void c3m_nu(const orc_c3m *c, double nu[ORC_C3M_NR][ORC_C3M_NG + ORC_C3M_
   nu[R_MR][G_H2O] = 1.0;
 }
 
+/* Test instrument, not part of the method (see orc_params.noise_eps): the
+ * key of the current cell and iteration, per thread. */
+static _Thread_local unsigned long long c3m_noise_key = 0ULL;
+
 void orc_c3m_source(const orc_c3m *c, const orc_params *p, const double *cell, double ROP_g,
                     double ROP_s, const double *X_g, const double *X_s, double rof,
                     double r[ORC_C3M_NR], double *dX_g, double *dX_s, double *dROP_g,
@@ -174,6 +192,8 @@ void orc_c3m_source(const orc_c3m *c, const orc_params *p, const double *cell, d
   double nu[ORC_C3M_NR][ORC_C3M_NG + ORC_C3M_NS];
   c3m_nu(c, nu);
   orc_c3m_rates(c, p, cell, ROP_g, ROP_s, X_g, X_s, r);
+  if (p->noise_eps > 0.0)
+    for (int j = 0; j < ORC_C3M_NR; ++j) r[j] += p->noise_eps * fabs(r[j]) * c3m_noise_u(c3m_noise_key, j);
   double omega[ORC_C3M_NG + ORC_C3M_NS];
   for (int k = 0; k < ORC_C3M_NG + ORC_C3M_NS; ++k) omega[k] = 0.0;
   for (int j = 0; j < ORC_C3M_NR; ++j) {
@@ -194,8 +214,16 @@ void orc_c3m_source(const orc_c3m *c, const orc_params *p, const double *cell, d
   }
 }
 
+static int c3m_integrate_cell_keyed(const orc_c3m *c, const orc_params *p, double *cell,
+                                    double tf, long long *iters, long long cell_id);
+
 int orc_c3m_integrate_cell(const orc_c3m *c, const orc_params *p, double *cell, double tf,
                            long long *iters) {
+  return c3m_integrate_cell_keyed(c, p, cell, tf, iters, 0);
+}
+
+static int c3m_integrate_cell_keyed(const orc_c3m *c, const orc_params *p, double *cell,
+                                    double tf, long long *iters, long long cell_id) {
   const int NG = ORC_C3M_NG, NS = ORC_C3M_NS, NX = ORC_C3M_NG + ORC_C3M_NS;
   const int W = p->dft_window;
   /* species masses per unit volume (kg/m^3), the conservative variables:
@@ -223,6 +251,10 @@ int orc_c3m_integrate_cell(const orc_c3m *c, const orc_params *p, double *cell, 
     for (int k = 0; k < NG; ++k) X[k] = m[k] / ROP_g;
     for (int k = 0; k < NS; ++k) X[NG + k] = m[NG + k] / ROP_s;
     double dROP_g, dROP_s, src[ORC_C3M_NG + ORC_C3M_NS];
+    c3m_noise_key = p->noise_eps > 0.0
+                        ? p->noise_seed ^ c3m_mix64((unsigned long long)cell_id * 0x100000001ULL +
+                                                   (unsigned long long)it)
+                        : 0ULL;
     orc_c3m_source(c, p, cell, ROP_g, ROP_s, X, X + NG, rof, r, dX, dX + NG, &dROP_g,
                    &dROP_s, src);
     double h = orc_step_size(p, NX, X, dX, t, tf);            /* Eqs 1-5 */
@@ -244,6 +276,8 @@ int orc_c3m_integrate_cell(const orc_c3m *c, const orc_params *p, double *cell, 
       }
     }
   }
+  if (iters) *iters = it;
+  if (it == 0) return status;   /* no step taken: the cell keeps its values */
   double ROP_g = 0.0, ROP_s = 0.0;
   for (int k = 0; k < NG; ++k) ROP_g += m[k];
   for (int k = 0; k < NS; ++k) ROP_s += m[NG + k];
@@ -254,7 +288,6 @@ int orc_c3m_integrate_cell(const orc_c3m *c, const orc_params *p, double *cell, 
   cell[V_EPS] = ep_s;
   cell[V_EPG] = ep_g;
   cell[V_ROG] = ROP_g / ep_g;
-  if (iters) *iters = it;
   return status;
 }
 
@@ -268,7 +301,7 @@ int orc_c3m_integrate(const orc_c3m *c, const orc_params *p, long long n, double
 #endif
   for (long long i = 0; i < n; ++i) {
     long long it = 0;
-    int st = orc_c3m_integrate_cell(c, p, &state[i * ld], tf, &it);
+    int st = c3m_integrate_cell_keyed(c, p, &state[i * ld], tf, &it, i);
     if (iters) iters[i] = it;
     if (status) status[i] = (unsigned char)st;
     if (st > worst) worst = st;

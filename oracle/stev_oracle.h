@@ -204,7 +204,8 @@ void orc_c3m_source(const orc_c3m *c, const orc_params *p, const double *cell, d
                     double r[ORC_C3M_NR], double *dX_g, double *dX_s, double *dROP_g,
                     double *dROP_s, double *src);
 
-/* One cell over [0, tf], in place on its 26 values.  Status as orc_integrate_cell. */
+/* One cell over [0, tf], in place on its 26 values (unchanged if it takes
+ * no step).  Status as orc_integrate_cell. */
 int orc_c3m_integrate_cell(const orc_c3m *c, const orc_params *p, double *cell, double tf,
                            long long *iters);
 

@@ -168,6 +168,8 @@ struct stev_ctx {
 constexpr long long kOrderMinCells = 4096;
 
 int stev_fail(stev_ctx *ctx, int code, const char *fmt, ...);
+// FP64 exp / log tables of the kernels (kXtabBytes, layout in stev_internal.h)
+void fill_xtab(double *xt);
 int dev_alloc(stev_ctx *ctx, void **p, size_t bytes);
 void dev_free(stev_ctx *ctx, void *p, size_t bytes);
 bool is_device_ptr(const void *p);

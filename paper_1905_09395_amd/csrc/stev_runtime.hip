@@ -223,6 +223,22 @@ extern "C" void stev_shutdown(stev_ctx *ctx) {
 // ---------------------------------------------------------------------------
 static inline int align16(int x) { return (x + 15) & ~15; }
 
+void fill_xtab(double *xt) {   // extended-precision values split into hi + lo
+  for (int j = 0; j < kExpTab; ++j) {
+    const long double v = exp2l((long double)j / kExpTab);
+    xt[2 * j] = (double)v;
+    xt[2 * j + 1] = (double)(v - (long double)xt[2 * j]);
+  }
+  double *lt = xt + 2 * kExpTab;
+  for (int j = 0; j < kLogTab; ++j) {
+    const double ic = (double)(1.0L / (1.0L + ((long double)j + 0.5L) / kLogTab));
+    const long double ml = -logl((long double)ic);
+    lt[3 * j] = ic;
+    lt[3 * j + 1] = (double)ml;
+    lt[3 * j + 2] = (double)(ml - (long double)lt[3 * j + 1]);
+  }
+}
+
 template <typename R>
 static void pack_blob(const stev_mech *m, std::vector<unsigned char> &blob, MechLayout &L) {
   const int n_s = m->n_s, n_r = m->n_r;
@@ -253,22 +269,7 @@ static void pack_blob(const stev_mech *m, std::vector<unsigned char> &blob, Mech
   L.off_jp = off;   off = align16(off + (n_s + 1) * L.jpitch * 4);
   L.bytes = std::max(off, 16);
   blob.assign(L.bytes, 0);
-  if constexpr (sizeof(R) == 8) {   // extended-precision values split into hi + lo
-    double *xt = reinterpret_cast<double *>(blob.data() + L.off_xtab);
-    for (int j = 0; j < kExpTab; ++j) {
-      const long double v = exp2l((long double)j / kExpTab);
-      xt[2 * j] = (double)v;
-      xt[2 * j + 1] = (double)(v - (long double)xt[2 * j]);
-    }
-    double *lt = xt + 2 * kExpTab;
-    for (int j = 0; j < kLogTab; ++j) {
-      const double ic = (double)(1.0L / (1.0L + ((long double)j + 0.5L) / kLogTab));
-      const long double ml = -logl((long double)ic);
-      lt[3 * j] = ic;
-      lt[3 * j + 1] = (double)ml;
-      lt[3 * j + 2] = (double)(ml - (long double)lt[3 * j + 1]);
-    }
-  }
+  if constexpr (sizeof(R) == 8) fill_xtab(reinterpret_cast<double *>(blob.data() + L.off_xtab));
   R *sp = reinterpret_cast<R *>(blob.data() + L.off_sp);
   for (int k = 0; k < n_s; ++k) {
     R *e = sp + k * kSpStride;

@@ -111,6 +111,35 @@ class MlpReport(C.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class C3mDesc(C.Structure):
+    """stev_c3m_desc: Table 2 constants, the Eq 31 / Eq 37 stoichiometry and
+    the molar masses (a dict as made by synth.make_c3m)."""
+    _fields_ = [("A_pyro", C.c_double), ("Ea_pyro", C.c_double),
+                ("A_wgs", C.c_double), ("Fp_wgs", C.c_double), ("Kf_wgs", C.c_double),
+                ("Eaf_wgs", C.c_double), ("Kr_wgs", C.c_double), ("Ear_wgs", C.c_double),
+                ("theta_G", C.c_double * 5), ("theta_C", C.c_double * 5),
+                ("A_stg", C.c_double), ("Fp_stg", C.c_double), ("Ea_stg", C.c_double),
+                ("A_cg", C.c_double), ("Fp_cg", C.c_double), ("Ea_cg", C.c_double),
+                ("A_meg", C.c_double), ("Ea_meg", C.c_double), ("beta_c", C.c_double),
+                ("A_cox", C.c_double), ("Ea_cox", C.c_double),
+                ("A_tox", C.c_double), ("Ea_tox", C.c_double),
+                ("A_coox", C.c_double), ("Ea_coox", C.c_double),
+                ("A_hox", C.c_double), ("Ea_hox", C.c_double),
+                ("A_meox", C.c_double), ("Ea_meox", C.c_double), ("A_mr", C.c_double),
+                ("nu_pyro", C.c_double * 11), ("nu_tox", C.c_double * 5),
+                ("W_g", C.c_double * 14), ("W_s", C.c_double * 4)]
+
+    @classmethod
+    def from_dict(cls, d):
+        c = cls()
+        for f, t in cls._fields_:
+            if hasattr(t, "_length_"):
+                getattr(c, f)[:] = [float(x) for x in d[f]]
+            else:
+                setattr(c, f, float(d[f]))
+        return c
+
+
 class LmaCfg(C.Structure):
     _fields_ = [("hidden", C.c_int32), ("iters", C.c_int32), ("n_samples", C.c_int64),
                 ("T_lo", C.c_double), ("T_hi", C.c_double), ("holdout_frac", C.c_double),
@@ -175,6 +204,13 @@ def load():
     L.stev_train_thermo_lma.argtypes = [vp, vp, C.POINTER(LmaCfg), C.POINTER(LmaReport), vp]
     L.stev_lma_normal_eq.argtypes = [vp, i32, i32, vp, i64, vp, vp, dbl, vp, vp,
                                      C.POINTER(dbl), vp]
+    L.stev_c3m_create.argtypes = [vp, C.POINTER(C3mDesc), C.POINTER(vp)]
+    L.stev_c3m_destroy.argtypes = [vp, vp]
+    L.stev_c3m_destroy.restype = None
+    L.stev_c3m_integrate.argtypes = [vp, vp, i64, vp, i64, i64, dbl, C.POINTER(Params), vp, vp,
+                                     C.POINTER(Stats)]
+    L.stev_c3m_model_flops.argtypes = [C.POINTER(dbl)]
+    L.stev_c3m_model_flops.restype = dbl
     L.stev_model_flops.argtypes = [vp, i32, C.POINTER(dbl)]
     L.stev_model_flops.restype = dbl
     L.stev_destroy_mechanism.argtypes = [vp, vp]
@@ -253,6 +289,28 @@ class Mechanism:
     def close(self):
         if self.h:
             self.ctx.lib.stev_destroy_mechanism(self.ctx.h, self.h)
+            self.h = None
+
+
+class C3m:
+    """A C3M description resident on the device (stev_c3m_create)."""
+
+    def __init__(self, ctx, desc):
+        self.ctx = ctx
+        self.desc = desc
+        d = C3mDesc.from_dict(desc)
+        h = C.c_void_p()
+        ctx._check(ctx.lib.stev_c3m_create(ctx.h, C.byref(d), C.byref(h)))
+        self.h = h
+
+    def model_flops(self):
+        tr = C.c_double()
+        f = self.ctx.lib.stev_c3m_model_flops(C.byref(tr))
+        return f, tr.value
+
+    def close(self):
+        if self.h:
+            self.ctx.lib.stev_c3m_destroy(self.ctx.h, self.h)
             self.h = None
 
 
@@ -336,6 +394,25 @@ class Context:
 
     def noalloc_max_cells(self):
         return int(self.lib.stev_noalloc_max_cells())
+
+    def c3m(self, desc):
+        return C3m(self, desc)
+
+    def c3m_integrate(self, c3m, state, dt_flow, params=None, iters=None, status=None,
+                      ld_cell=None, ld_var=1, n_cells=None, allow_failed=False):
+        """Integrate gas-solid cells in place; state is [n_cells, 26], or any
+        layout given by n_cells, ld_cell and ld_var."""
+        params = params or default_params()
+        n = int(state.shape[0]) if n_cells is None else int(n_cells)
+        if ld_cell is None:
+            ld_cell = int(state.shape[1])
+        _after_torch()
+        st = Stats()
+        rc = self.lib.stev_c3m_integrate(self.h, c3m.h, n, _ptr(state)[0], int(ld_cell),
+                                         int(ld_var), float(dt_flow), C.byref(params),
+                                         _ptr(iters)[0], _ptr(status)[0], C.byref(st))
+        self._check(rc, (STEV_OK, STEV_ECELLS) if allow_failed else (STEV_OK,))
+        return rc, st.as_dict()
 
     def integrate_batched(self, mechs, Ts, Ps, Ys, dt_flow, params=None, iters=None,
                           status=None, allow_failed=False):

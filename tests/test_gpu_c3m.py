@@ -1,0 +1,251 @@
+"""GPU parity of the multiphase C3M chemistry (Sec 7.2): stev_c3m_integrate
+through the C ABI against the FP64 oracle, every cell and every one of the
+26 values, at sizes that span several waves and a ragged tail; the full
+262 144-cell field of the benchmark on a seeded sample; edge cases, layouts,
+failure statuses and launch-shape independence."""
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1905_09395_amd import stev, synth
+from tests.gpu_common import say
+
+pytestmark = pytest.mark.gpu
+DT = 1e-3
+# FP64: 1e-9 relative on every phase value and every mass fraction above
+# 1e-10; FP32: 1e-4 on the phase values, 1e-3 on mass fractions above 1e-6
+TOL = {stev.F64: (1e-9, 1e-9, 1e-10), stev.F32: (1e-4, 1e-3, 1e-6)}
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    assert torch.cuda.is_available(), "GPU test needs a HIP device"
+    c = stev.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def c3(ctx):
+    d = synth.make_c3m()
+    g = ctx.c3m(d)
+    yield g, oracle.C3M(d)
+    g.close()
+
+
+def run_gpu(ctx, g, state, prec=stev.F64, device=True, **kw):
+    import torch
+    dtype = torch.float64 if prec == stev.F64 else torch.float32
+    n = len(state)
+    if device:
+        s = torch.tensor(state, dtype=dtype, device="cuda")
+        it = torch.zeros(n, dtype=torch.int32, device="cuda")
+        st = torch.zeros(n, dtype=torch.uint8, device="cuda")
+    else:
+        s = np.ascontiguousarray(state, dtype=np.float64 if prec == stev.F64 else np.float32)
+        it = np.zeros(n, np.int32)
+        st = np.zeros(n, np.uint8)
+    allow = kw.pop("allow_failed", False)
+    prm = stev.default_params(precision=prec, **kw)
+    rc, stats = ctx.c3m_integrate(g, s, DT, params=prm, iters=it, status=st,
+                                  allow_failed=allow)
+    if device:
+        torch.cuda.synchronize()
+        s, it, st = s.cpu().double().numpy(), it.cpu().numpy(), st.cpu().numpy()
+    return dict(state=np.asarray(s, dtype=np.float64), iters=np.asarray(it, np.int64),
+                status=np.asarray(st), rc=rc, stats=stats)
+
+
+# FP32 ensemble (full-length runs): the oracle on inputs moved by the
+# rounding of FP32 (2.4e-7 relative) and with every rate perturbed at each
+# step by 2e-6 of itself, the error an FP32 evaluation carries (the largest
+# exponentials take arguments Ea/T ~ 25 whose FP32 rounding, 25 * 2^-24 =
+# 1.5e-6, is their relative error); 16 members.  Cells whose spread exceeds
+# a hundredth of the tolerance are ill-conditioned at FP32: they must lie
+# within twice the spread; all others within the tolerance.
+ENS32 = dict(eps=2.4e-7, noise=2e-6, members=16, factor=2.0)
+
+
+def oracle_c3m_ensemble(oc, st):
+    o = oracle.c3m_integrate(oc, st, DT)
+    spread = np.zeros((len(st), 21))
+    for i in range(ENS32["members"]):
+        rng = np.random.default_rng(700 + i)
+        p = st * (1 + ENS32["eps"] * rng.uniform(-1, 1, st.shape))
+        r = oracle.c3m_integrate(oc, p, DT, noise_eps=ENS32["noise"], noise_seed=300 + i)
+        spread = np.maximum(spread, np.abs(r["state"][:, 5:26] - o["state"][:, 5:26]))
+    o["spread"] = spread            # columns: ep_s, rho_s, d_p, X_g, X_s
+    return o
+
+
+def judge_c3m(g, o, prec, label):
+    tP, tX, thr = TOL[prec]
+    a, b = g["state"], o["state"]
+    phase = [3, 4, 5]                     # ep_g, rho_g, ep_s
+    rel_p = np.abs(a[:, phase] - b[:, phase]) / np.abs(b[:, phase])
+    X = b[:, 8:26]
+    mask = X > thr
+    rel_x = np.where(mask, np.abs(a[:, 8:26] - X) / np.where(mask, X, 1.0), 0.0)
+    held = [0, 1, 2, 6, 7]
+    same_held = np.array_equal(a[:, held], b[:, held]) if prec == stev.F64 else \
+        np.allclose(a[:, held], b[:, held], rtol=1e-6)
+    it_eq = np.array_equal(g["iters"], o["iters"])
+    say(f"[{label}] n={len(a)} max rel phase={rel_p.max():.2e} max rel X={rel_x.max():.2e} "
+        f"iters equal={it_eq} (mismatch {int(np.sum(g['iters'] != o['iters']))}) "
+        f"held values unchanged={same_held}")
+    assert np.array_equal(g["status"], o["status"]), label
+    assert same_held, label
+    ok = (rel_p.max(axis=1) <= tP) & (rel_x.max(axis=1) <= tX)
+    say(f"    cells held to the stated tolerance: {int(ok.sum())} of {len(ok)}")
+    if "spread" in o:
+        sp = o["spread"]
+        spx = np.where(mask, sp[:, 3:21] / np.where(mask, X, 1.0), 0.0)
+        spp = sp[:, [0]] / np.abs(b[:, [5]])
+        ill = (spx.max(axis=1) > tX / 100) | (spp.max(axis=1) > tP / 100)
+        errx = np.abs(a[:, 8:26] - X)
+        allow = np.maximum(tX * X, ENS32["factor"] * sp[:, 3:21])
+        ok_ill = np.all(np.where(mask, errx <= allow, True), axis=1) & (rel_p.max(axis=1) <= tP)
+        bad = np.where(~np.where(ill, ok_ill, ok))[0]
+        say(f"    ill-conditioned at this precision: {int(ill.sum())} "
+            f"{np.where(ill)[0][:8].tolist()}; outside the allowance: {bad.tolist()[:8]}")
+        for c in np.where(ill & ~ok)[0][:4]:
+            k = int(np.argmax(rel_x[c]))
+            say(f"    cell {c}: species {k} X={X[c, k]:.3e} rel err {rel_x[c, k]:.2e} "
+                f"rel spread {spx[c, k]:.2e}")
+        assert len(bad) == 0, label
+    else:
+        assert ok.all(), label
+    if prec == stev.F64:
+        assert it_eq, label
+    return rel_p.max(), rel_x.max()
+
+
+@pytest.mark.parametrize("prec", [stev.F64, stev.F32])
+def test_c3m_field_every_cell(ctx, c3, prec):
+    g, oc = c3
+    st = synth.make_c3m_cells(2000, seed=11)
+    say(f"C3M 2000 cells prec={prec}")
+    o = oracle.c3m_integrate(oc, st, DT)
+    r = run_gpu(ctx, g, st, prec)
+    say(f"  iterations: min {r['iters'].min()} max {r['iters'].max()} total {r['iters'].sum()}; "
+        f"kernel {r['stats']['kernel_ms']:.2f} ms")
+    assert r["stats"]["total_iters"] == r["iters"].sum()
+    assert r["stats"]["max_cell_iters"] == r["iters"].max()
+    judge_c3m(r, o, prec, f"c3m/{prec}")
+
+
+def test_c3m_sizes_layouts_and_host_arrays(ctx, c3):
+    import torch
+    g, oc = c3
+    st = synth.make_c3m_cells(130, seed=12)
+    for n in (1, 2, 63, 65, 130):
+        o = oracle.c3m_integrate(oc, st[:n], DT)
+        judge_c3m(run_gpu(ctx, g, st[:n]), o, stev.F64, f"n={n}")
+    o = oracle.c3m_integrate(oc, st, DT)
+    # variable-major layout: value v of cell c at v * n + c
+    sv = torch.tensor(np.ascontiguousarray(st.T), dtype=torch.float64, device="cuda")
+    it = torch.zeros(130, dtype=torch.int32, device="cuda")
+    ctx.c3m_integrate(g, sv, DT, ld_cell=1, ld_var=130, n_cells=130, iters=it)
+    r = dict(state=sv.cpu().numpy().T.copy(), iters=it.cpu().numpy().astype(np.int64),
+             status=np.zeros(130, np.uint8))
+    judge_c3m(r, o, stev.F64, "variable-major")
+    # host arrays are staged by the library
+    judge_c3m(run_gpu(ctx, g, st, device=False), o, stev.F64, "host")
+    # zero cells; zero flow step
+    z = torch.zeros((0, 26), dtype=torch.float64, device="cuda")
+    rc, s0 = ctx.c3m_integrate(g, z, DT)
+    assert rc == stev.STEV_OK and s0["n_cells"] == 0
+    import torch as _t
+    s1 = _t.tensor(st, device="cuda")
+    ctx.c3m_integrate(g, s1, 0.0)
+    assert np.array_equal(s1.cpu().numpy(), st)
+
+
+def test_c3m_failure_statuses(ctx, c3):
+    g, oc = c3
+    st = synth.make_c3m_cells(40, seed=13)
+    st[7, 0] = np.nan                   # a non-finite gas temperature fails the cell
+    o = oracle.c3m_integrate(oc, st, DT, max_iters=150)
+    r = run_gpu(ctx, g, st, max_iters=150, allow_failed=True)
+    assert r["rc"] == stev.STEV_ECELLS
+    assert r["status"][7] == 1 and o["status"][7] == 1
+    assert np.array_equal(r["status"], o["status"])
+    assert np.any(r["status"] == 2)
+    ok = o["status"] != 1
+    assert np.array_equal(r["iters"][ok], o["iters"][ok])
+    assert r["stats"]["n_failed"] == int(np.sum(o["status"] != 0))
+
+
+def test_c3m_results_independent_of_launch_shape(ctx, c3):
+    """A cell's result is a function of the cell alone: launch shape, refill
+    cadence and the cell's position in the field change no bit."""
+    g, _ = c3
+    st = synth.make_c3m_cells(500, seed=14)
+    for prec in (stev.F64, stev.F32):
+        a = run_gpu(ctx, g, st, prec)
+        b = run_gpu(ctx, g, st, prec, waves_per_wg=1, grid_wgs=3, compact_every=5)
+        sh = np.concatenate([st[250:], st, st[:250]])
+        c = run_gpu(ctx, g, sh, prec)
+        for r in (b, {k: (v[250:750] if isinstance(v, np.ndarray) else v) for k, v in c.items()}):
+            assert np.array_equal(a["state"], r["state"]) and np.array_equal(a["iters"], r["iters"])
+
+
+def test_c3m_rejections(ctx, c3):
+    import torch
+    g, _ = c3
+    s = torch.tensor(synth.make_c3m_cells(4, seed=1), device="cuda")
+    for kw in (dict(thermo=stev.THERMO_MLP), dict(stab_limit=1), dict(lanes_per_cell=8),
+               dict(dft_window=7)):
+        with pytest.raises(stev.StevError) as e:
+            ctx.c3m_integrate(g, s, DT, params=stev.default_params(**kw))
+        assert e.value.code == stev.STEV_EINVAL
+    bad = dict(synth.make_c3m())
+    bad["W_g"] = list(bad["W_g"])
+    bad["W_g"][3] = 0.0
+    with pytest.raises(stev.StevError) as e:
+        ctx.c3m(bad)
+    assert e.value.code == stev.STEV_EINVAL
+
+
+def test_c3m_full_field_sampled(ctx, c3):
+    """The benchmark's 262 144-cell field at its launch configuration: every
+    cell finishes, the phases keep their total mass and the fractions their
+    sums; a seeded sample is recomputed by the oracle."""
+    g, oc = c3
+    st = synth.make_c3m_cells(262144, seed=108)
+    for prec in (stev.F64, stev.F32):
+        say(f"C3M full 262144 prec={prec}")
+        r = run_gpu(ctx, g, st, prec)
+        assert np.all(r["status"] == 0)
+        m0 = st[:, 3] * st[:, 4] + st[:, 5] * st[:, 6]
+        s = r["state"]
+        m1 = s[:, 3] * s[:, 4] + s[:, 5] * s[:, 6]
+        tol = 1e-12 if prec == stev.F64 else 2e-5
+        assert np.max(np.abs(m1 / m0 - 1)) < tol
+        assert np.max(np.abs(s[:, 8:22].sum(axis=1) - 1)) < tol
+        assert np.max(np.abs(s[:, 22:26].sum(axis=1) - 1)) < tol
+        edges = np.asarray(stev.load_bin_edges() + [2 ** 34])
+        assert np.array_equal(np.asarray(r["stats"]["load_hist"]),
+                              np.histogram(r["iters"], bins=edges)[0])
+        idx = synth.subsample(len(st), 2048, seed=90 + prec)
+        o = (oracle.c3m_integrate(oc, st[idx], DT) if prec == stev.F64
+             else oracle_c3m_ensemble(oc, st[idx]))
+        sub = {k: (v[idx] if isinstance(v, np.ndarray) else v) for k, v in r.items()}
+        judge_c3m(sub, o, prec, f"c3m full/{prec}")
+
+
+@pytest.mark.parametrize("prec", [stev.F64, stev.F32])
+def test_c3m_every_cell_short_run_strict(ctx, c3, prec):
+    """Every cell of the full 262 144-cell field, 25 steps (status 2 for the
+    cells that would go on), held to the stated tolerance with no exemption:
+    before depletion and the Eq 3 90 % steps have amplified anything, no
+    cell is ill-conditioned at either precision."""
+    g, oc = c3
+    st = synth.make_c3m_cells(262144, seed=108)
+    say(f"C3M 262144 cells, 25 steps, prec={prec}")
+    r = run_gpu(ctx, g, st, prec, max_iters=25, allow_failed=True)
+    o = oracle.c3m_integrate(oc, st, DT, max_iters=25)
+    assert np.all(r["iters"] == 25)
+    judge_c3m(r, o, prec, f"c3m 25 steps/{prec}")

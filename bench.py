@@ -14,6 +14,9 @@ Other workloads (one JSON line each, same keys):
                       autotuned launch shape), against 64 plain calls
   --workload mlp      19 species, 1 048 576 cells, FP32 with the thermo
                       network against FP32 polynomials
+  --workload c3m      the multiphase C3M gasification chemistry (Sec 7.2):
+                      262 144 random gas-solid cells of 26 values,
+                      dt_flow = 1e-3 s
   --workload serve    Poisson arrivals of requests of log-uniform size in
                       [1024, 524288] cells over 6-, 19- and 53-species
                       mechanisms, FP32 + thermo network, host-resident
@@ -21,7 +24,7 @@ Other workloads (one JSON line each, same keys):
                       latency against plain per-request launches
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision f64|f32]
-                  [--workload plain|batched|mlp|serve]
+                  [--workload plain|batched|mlp|serve|c3m]
 """
 
 import argparse
@@ -434,6 +437,87 @@ def run_mlp(args):
     return out
 
 
+def run_c3m(args):
+    """The multiphase C3M gasification field: 262 144 random gas-solid cells
+    (26 values each), integrated over dt_flow = 1e-3 s."""
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_1905_09395_amd import stev, synth
+    dev = torch.device("cuda:0")
+    dt = 1e-3
+    n = args.cells
+    desc = synth.make_c3m()
+    st = synth.make_c3m_cells(n, seed=108)
+    ctx = stev.Context(0)
+    ctx.set_stream(torch.cuda.current_stream(dev))
+    g = ctx.c3m(desc)
+    prec = stev.F64 if args.precision == "f64" else stev.F32
+    dtype = torch.float64 if prec == stev.F64 else torch.float32
+    S0 = torch.tensor(st, dtype=dtype, device=dev)
+    Sw = S0.clone()
+    prm = stev.default_params(precision=prec)
+
+    def step():
+        Sw.copy_(S0)
+        return ctx.c3m_integrate(g, Sw, dt, params=prm)[1]
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    kms, its = [], []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        r = step()
+        kms.append(r["launch_ms"])
+        its.append(r["total_iters"])
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    flops, transc = g.model_flops()
+    k_ms = float(np.mean(kms))
+    achieved = float(np.mean(its)) * flops / (k_ms * 1e-3) / 1e12
+    rsz = 8 if prec == stev.F64 else 4
+    out = base_record(args, n * args.steps / el, el, args.precision,
+                      f"multiphase C3M gasification (Sec 7.2, Eqs 31-56, Table 2): {n} random "
+                      f"gas-solid cells of 26 values (T_g 900-1400 K, P 1-15 atm, eps_s "
+                      f"0.02-0.3, d_p 50-500 um, Dirichlet gas and solid fractions), "
+                      f"dt_flow=1e-3 s, {args.precision}",
+                      cells=n, dt_flow=dt, lanes_per_cell=1, waves_per_wg=r["waves_per_wg"],
+                      grid_wgs=r["grid_wgs"],
+                      cell_iterations_per_step=int(np.mean(its)),
+                      max_cell_iterations=r["max_cell_iters"],
+                      load_curve=stev.load_curve(r["load_hist"]))
+    out["roofline"] = {"bound": "alu", "achieved": achieved, "peak": PEAK[args.precision],
+                       "unit": "TFLOP/s", "frac": achieved / PEAK[args.precision],
+                       "traffic": None, "kernel_ms": k_ms,
+                       "model_flop_per_cell_iter": flops,
+                       "transcendentals_per_cell_iter": transc,
+                       "state_bytes_per_launch": 2 * 26 * rsz * n}
+    if not args.no_cpu:
+        cores = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count() or 1
+        oc = oracle.C3M(desc)
+        m, tot_c, tot_s, seed = 256, 0, 0.0, 900
+        while tot_s < 12.0 and m <= 65536:
+            idx = synth.subsample(n, m, seed=seed)
+            seed += 1
+            t1 = time.perf_counter()
+            oracle.c3m_integrate(oc, st[idx], dt, nthreads=cores)
+            e = time.perf_counter() - t1
+            tot_c += m
+            tot_s += e
+            if e < 3.0:
+                m *= 2
+        out["cpu_baseline"] = {"value": tot_c / tot_s, "unit": "cells/s", "cores": cores,
+                               "kind": "oracle",
+                               "sample": f"{tot_c} cells drawn (seeded) from the same field in "
+                                         f"batches of doubling size, {tot_s:.1f} s of FP64 "
+                                         f"oracle time over {cores} host threads"}
+    g.close()
+    ctx.close()
+    return out
+
+
 def run_serve(args):
     """Poisson-arrival serving against plain per-request launches."""
     import threading
@@ -586,7 +670,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--probe", action="store_true",
                     help="counter-calibration run: one plain copy, then one step")
-    ap.add_argument("--workload", default="plain", choices=["plain", "batched", "mlp", "serve"])
+    ap.add_argument("--workload", default="plain",
+                    choices=["plain", "batched", "mlp", "serve", "c3m"])
     ap.add_argument("--traffic-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="CPU only: write the HBM traffic summary from two counter runs")
     ap.add_argument("--pmc-summary", nargs="+", metavar="CSV",
@@ -612,7 +697,8 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.workload != "plain":
-        out = {"batched": run_batched, "mlp": run_mlp, "serve": run_serve}[args.workload](args)
+        out = {"batched": run_batched, "mlp": run_mlp, "serve": run_serve,
+               "c3m": run_c3m}[args.workload](args)
         print(json.dumps(out), flush=True)
         return
     dev = torch.device("cuda:0")

@@ -5,8 +5,8 @@
 // forward Euler (Eq 18) on the species masses, DFT damping (Eqs 8-14) of the
 // one reversible reaction (water-gas shift) and variable loading (Sec 2.4).
 //
-// One cell per lane.  A cell's 18 species masses, its ring and rOF live in
-// registers; everything that depends only on the phase temperatures and the
+// One cell per lane.  A cell's 18 species masses and rOF live in registers,
+// its ring of 13 WGS samples in a column of LDS; everything that depends only on the phase temperatures and the
 // pressure (all exponentials of Table 2's activation temperatures and the
 // WGS pressure factor) is evaluated once when the cell is loaded, since the
 // chemistry step holds T_g, T_s and P_g.  A lane that finishes its cell
@@ -83,9 +83,14 @@ __device__ __forceinline__ R powp(const CM<R> &M, R x, R o) {
   return x > R(0) ? M.ex(o * M.lg(x)) : R(0);
 }
 
+constexpr int kMaxWaves = 4;
+
 template <typename R>
-__global__ void __launch_bounds__(256) stev_c3m_persistent(const C3mArgs a) {
+__global__ void __launch_bounds__(64 * kMaxWaves, 2) stev_c3m_persistent(const C3mArgs a) {
   __shared__ double xt[kXtabBytes / 8];
+  // the WGS rings, one column per lane: slot q of lane l of wave w at
+  // ring_lds[(w * kWin + q) * 64 + l]
+  __shared__ R ring_lds[kMaxWaves * kWin * 64];
   CM<R> M;
   if constexpr (sizeof(R) == 8) {
     for (int i = threadIdx.x; i < kXtabBytes / 8; i += blockDim.x) xt[i] = a.xtab[i];
@@ -106,14 +111,15 @@ __global__ void __launch_bounds__(256) stev_c3m_persistent(const C3mArgs a) {
   int st = 0, it = 0, rs = 0;
   double t = 0.0;
   R m[NX];                     // species masses per unit volume, kg/m^3
-  R rof = R(1), ring[kWin];
+  R rof = R(1);
+  R *const ring = ring_lds + (threadIdx.x >> 6) * kWin * 64 + lane;   // slot q at ring[q * 64]
   // per-cell constants (functions of T_g, T_s, P_g, rho_s, d_p)
   R k_pyro = 0, kf_w = 0, kr_w = 0, k_stg = 0, k_cg = 0, k_meg = 0, k_cox = 0, k_tox = 0,
     k_coox = 0, k_hox = 0, k_meox = 0, P = 1, lnP = 0, inv_rho_s = 1, geo = 0, eps_tot = 1;
 #pragma unroll
   for (int k = 0; k < NX; ++k) m[k] = R(1);
 #pragma unroll
-  for (int q = 0; q < kWin; ++q) ring[q] = R(0);
+  for (int q = 0; q < kWin; ++q) ring[q * 64] = R(0);
 
   long long sum_it = 0, max_it = 0, n_fail = 0;
   const int K = a.compact_every > 0 ? a.compact_every : 1;
@@ -354,23 +360,23 @@ __global__ void __launch_bounds__(256) stev_c3m_persistent(const C3mArgs a) {
     // WGS ring of undamped r h (Eq 8), |DFT| at bins 0 and 4..6 (Eqs 9-10),
     // rOF (Eqs 11-13); slots relative to the cell's own steps
     if (a.dft_on) {
-      const R x = r_wgs * hR;
-#pragma unroll
-      for (int q = 0; q < kWin; ++q) ring[q] = (commit && rs == q) ? x : ring[q];
+      if (commit) ring[rs * 64] = r_wgs * hR;
       rs = commit ? (rs == kWin - 1 ? 0 : rs + 1) : rs;
       if (commit && it >= kWin) {
+        const R x0 = ring[0];
         R sp[6], dm[6];
-        R S = ring[0];
+        R S = x0;
 #pragma unroll
         for (int q = 1; q <= 6; ++q) {
-          sp[q - 1] = ring[q] + ring[kWin - q];
-          dm[q - 1] = ring[q] - ring[kWin - q];
+          const R u = ring[q * 64], v = ring[(kWin - q) * 64];
+          sp[q - 1] = u + v;
+          dm[q - 1] = u - v;
           S += sp[q - 1];
         }
         R M2 = R(0);
 #pragma unroll
         for (int kb = 4; kb <= 6; ++kb) {
-          R re = ring[0], im = R(0);
+          R re = x0, im = R(0);
 #pragma unroll
           for (int q = 0; q < 6; ++q) {
             const int j = (kb * (q + 1)) % 13;
@@ -524,7 +530,7 @@ extern "C" int stev_c3m_integrate(stev_ctx *ctx, const stev_c3m *c, int64_t n_ce
   const void *fn = p.precision == STEV_F64
                        ? reinterpret_cast<const void *>(&stev_c3m_persistent<double>)
                        : reinterpret_cast<const void *>(&stev_c3m_persistent<float>);
-  const int waves = p.waves_per_wg > 0 ? p.waves_per_wg : 4;
+  const int waves = p.waves_per_wg > 0 ? p.waves_per_wg : kMaxWaves;
   const int block = 64 * waves;
   int occ = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fn, block, 0) != hipSuccess || occ < 1)

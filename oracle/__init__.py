@@ -41,7 +41,9 @@ class _Mech(C.Structure):
                 ("W", C.c_void_p), ("nasa_lo", C.c_void_p), ("nasa_hi", C.c_void_p),
                 ("T_mid", C.c_void_p), ("rxn_ptr", C.c_void_p), ("sp_idx", C.c_void_p),
                 ("nu", C.c_void_p), ("order", C.c_void_p), ("A", C.c_void_p),
-                ("b", C.c_void_p), ("Ea", C.c_void_p), ("rev", C.c_void_p)]
+                ("b", C.c_void_p), ("Ea", C.c_void_p), ("rev", C.c_void_p),
+                ("mlp_H", C.c_int), ("mlp_prm", C.c_void_p), ("mlp_mean", C.c_void_p),
+                ("mlp_sd", C.c_void_p), ("mlp_T_lo", C.c_double), ("mlp_T_hi", C.c_double)]
 
 
 class _Params(C.Structure):
@@ -129,7 +131,7 @@ def lib():
         L.orc_integrate_cell.restype = C.c_int
         L.orc_integrate.argtypes = [C.POINTER(_Mech), C.POINTER(_Params), C.c_longlong, dp, dp,
                                     dp, C.c_longlong, C.c_double, C.POINTER(C.c_longlong),
-                                    C.POINTER(C.c_ubyte), dp, dp, C.c_int]
+                                    C.POINTER(C.c_ubyte), dp, dp, C.c_int, dp]
         L.orc_integrate.restype = C.c_int
         L.orc_nasa_targets.argtypes = [C.POINTER(_Mech), C.c_longlong, dp, dp, dp]
         L.orc_mlp_n_params.argtypes = [C.c_int, C.c_int]
@@ -185,6 +187,22 @@ class OracleMech:
                                                     "A", "b", "Ea", "rev")])
         self.n_s = int(mech["n_s"])
         self.n_r = int(mech["n_r"])
+
+    def with_network(self, H, prm, mean, sd, T_lo, T_hi):
+        """A copy whose thermo (cp/R, h/R) comes from a network inside
+        [T_lo, T_hi] (Sec 3): FP64 parameters in the orc_mlp_forward layout,
+        z-score means and deviations [2 n_s] (cp/R first, then h/R)."""
+        o = OracleMech(self.mech)
+        o._keep.update(mlp_prm=np.ascontiguousarray(prm, dtype=np.float64),
+                       mlp_mean=np.ascontiguousarray(mean, dtype=np.float64),
+                       mlp_sd=np.ascontiguousarray(sd, dtype=np.float64))
+        o.c.mlp_H = int(H)
+        o.c.mlp_prm = o._keep["mlp_prm"].ctypes.data
+        o.c.mlp_mean = o._keep["mlp_mean"].ctypes.data
+        o.c.mlp_sd = o._keep["mlp_sd"].ctypes.data
+        o.c.mlp_T_lo = float(T_lo)
+        o.c.mlp_T_hi = float(T_hi)
+        return o
 
 
 def make_params(**kw):
@@ -278,7 +296,8 @@ def integrate_cell(om, T, P, Y, tf, trace_cap=0, **kw):
 
 
 def integrate(om, T, P, Y, tf, nthreads=0, **kw):
-    """Integrate all cells; returns dict(T, Y, iters, status, margin_dft, margin_y)."""
+    """Integrate all cells; returns dict(T, Y, iters, status, margin_dft, margin_y,
+    margin_h) (the margins are diagnostics: see orc_integrate_cell_keyed)."""
     prm = make_params(**kw)
     T = np.array(T, dtype=np.float64).copy()
     P = np.ascontiguousarray(P, dtype=np.float64)
@@ -288,11 +307,13 @@ def integrate(om, T, P, Y, tf, nthreads=0, **kw):
     status = np.zeros(n, dtype=np.uint8)
     md = np.zeros(n)
     my = np.zeros(n)
+    mh = np.zeros(n)
     lib().orc_integrate(C.byref(om.c), C.byref(prm), n, _p(T), _p(P), _p(Y), Y.shape[1],
                         float(tf), iters.ctypes.data_as(C.POINTER(C.c_longlong)),
                         status.ctypes.data_as(C.POINTER(C.c_ubyte)), _p(md), _p(my),
-                        int(nthreads))
-    return dict(T=T, Y=Y, iters=iters, status=status, margin_dft=md, margin_y=my)
+                        int(nthreads), _p(mh))
+    return dict(T=T, Y=Y, iters=iters, status=status, margin_dft=md, margin_y=my,
+                margin_h=mh)
 
 
 def nasa_targets(om, T):

@@ -109,6 +109,16 @@ void orc_source_keyed(const orc_mech *m, const orc_params *p, double T, double P
     g[k] = th[1] - th[2];
     C[k] = rho * orc_ystarstar(Y[k], p->alpha) / m->W[k];
   }
+  if (m->mlp_prm && T >= m->mlp_T_lo && T <= m->mlp_T_hi) {   /* Sec 3 */
+    double *z = (double *)malloc(sizeof(double) * 2 * (size_t)n_s);
+    double x = (T - 1650.0) / 1350.0;
+    orc_mlp_forward(m->mlp_H, 2 * n_s, m->mlp_prm, 1, &x, z);
+    for (int k = 0; k < n_s; ++k) {
+      cp_R[k] = z[k] * m->mlp_sd[k] + m->mlp_mean[k];
+      h_RT[k] = (z[n_s + k] * m->mlp_sd[n_s + k] + m->mlp_mean[n_s + k]) / T;
+    }
+    free(z);
+  }
 
   for (int k = 0; k < n_s; ++k) omega[k] = 0.0;
 
@@ -316,6 +326,23 @@ double orc_rof_next(double rof, int ringing_eq, const orc_params *p) {
   return fmax(r, p->rof_min);
 }
 
+/* Diagnostic (no part of the result): where Eq 3's minimum sets the step,
+ * the relative gap between its two smallest candidates, (c2 - c1) / c1;
+ * +inf where t* does not bind (Delta t_max or the end of the flow step is
+ * smaller) or only one species is consumed. */
+static double orc_eq3_gap(const orc_params *p, int n_s, const double *Y, const double *dYdt,
+                          double t, double tf) {
+  double c1 = INFINITY, c2 = INFINITY;
+  for (int k = 0; k < n_s; ++k) {   /* the candidates of Eqs 1-3 */
+    double ys = Y[k] < 1.0e-20 ? 1.0 : 0.9 * Y[k];
+    double cand = fmin(p->ystep_max, ys) / fmax(-dYdt[k], 1.0e-30);
+    if (cand < c1) { c2 = c1; c1 = cand; }
+    else if (cand < c2) c2 = cand;
+  }
+  if (c1 > tf * p->delta_max || c1 > tf - t || !isfinite(c2)) return INFINITY;
+  return (c2 - c1) / c1;
+}
+
 /* ---------------------------------------------------------------------------
  * One cell over one flow step (Sections 2.1-2.4, Eq 18).
  * Loop: rates with rOF_t -> step size -> forward Euler -> ring/DFT -> rOF_{t+1};
@@ -327,13 +354,14 @@ int orc_integrate_cell(const orc_mech *m, const orc_params *p, double *T_io,
                        double *margin_dft, double *margin_y,
                        double *h_trace, long long trace_cap) {
   return orc_integrate_cell_keyed(m, p, T_io, P, Y_io, tf, iters, margin_dft, margin_y,
-                                  h_trace, trace_cap, 0);
+                                  h_trace, trace_cap, 0, NULL);
 }
 
 int orc_integrate_cell_keyed(const orc_mech *m, const orc_params *p, double *T_io,
                              double P, double *Y_io, double tf, long long *iters,
                              double *margin_dft, double *margin_y,
-                             double *h_trace, long long trace_cap, long long cell) {
+                             double *h_trace, long long trace_cap, long long cell,
+                             double *margin_h) {
   int n_s = m->n_s, n_r = m->n_r, W = p->dft_window;
   size_t nd = (size_t)(4 * n_s + 2 * n_r + (W > 0 ? n_r * W + W : 0));
   double *buf = (double *)calloc(nd, sizeof(double));
@@ -345,7 +373,7 @@ int orc_integrate_cell_keyed(const orc_mech *m, const orc_params *p, double *T_i
   double T = *T_io, t = 0.0;
   long long it = 0;
   int status = 0;
-  double mdft = INFINITY, my = INFINITY;
+  double mdft = INFINITY, my = INFINITY, mh = INFINITY;
   memcpy(Y, Y_io, sizeof(double) * (size_t)n_s);
   for (int j = 0; j < n_r; ++j) rOF[j] = 1.0;                 /* Eq 11 */
 
@@ -360,6 +388,10 @@ int orc_integrate_cell_keyed(const orc_mech *m, const orc_params *p, double *T_i
       if (d < my) my = d;
     }
     double h = orc_step_size(p, n_s, Y, dYdt, t, tf);
+    if (margin_h) {
+      double g = orc_eq3_gap(p, n_s, Y, dYdt, t, tf);
+      if (g < mh) mh = g;
+    }
     if (p->stab_limit) {                                       /* Eq 25 */
       double na = orc_jacobian_inf_norm(m, p, T, P, Y, rOF, NULL);
       if (na > 0.0) h = fmin(h, 2.0 / na);
@@ -395,6 +427,7 @@ int orc_integrate_cell_keyed(const orc_mech *m, const orc_params *p, double *T_i
   if (iters) *iters = it;
   if (margin_dft) *margin_dft = mdft;
   if (margin_y) *margin_y = my;
+  if (margin_h) *margin_h = mh;
   free(buf);
   return status;
 }
@@ -402,7 +435,7 @@ int orc_integrate_cell_keyed(const orc_mech *m, const orc_params *p, double *T_i
 int orc_integrate(const orc_mech *m, const orc_params *p, long long n,
                   double *T, const double *P, double *Y, long long ld,
                   double tf, long long *iters, unsigned char *status,
-                  double *margin_dft, double *margin_y, int nthreads) {
+                  double *margin_dft, double *margin_y, int nthreads, double *margin_h) {
   int worst = 0;
   if (p->dft_window > 0) orc_dft_table(p->dft_window);   /* before the threads start */
 #ifdef _OPENMP
@@ -411,9 +444,10 @@ int orc_integrate(const orc_mech *m, const orc_params *p, long long n,
 #endif
   for (long long c = 0; c < n; ++c) {
     long long it = 0;
-    double md = 0.0, my = 0.0;
+    double md = 0.0, my = 0.0, mh = 0.0;
     int st = orc_integrate_cell_keyed(m, p, &T[c], P[c], &Y[c * ld], tf, &it, &md,
-                                      &my, NULL, 0, c);
+                                      &my, NULL, 0, c, margin_h ? &mh : NULL);
+    if (margin_h) margin_h[c] = mh;
     if (iters) iters[c] = it;
     if (status) status[c] = (unsigned char)st;
     if (margin_dft) margin_dft[c] = md;

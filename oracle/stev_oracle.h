@@ -34,6 +34,14 @@ typedef struct {
   const double *b;             /* [n_r] */
   const double *Ea;            /* [n_r] J/mol */
   const unsigned char *rev;    /* [n_r] */
+  /* Optional thermo network (Sec 3), NULL prm for the polynomials: inside
+   * [T_lo, T_hi] cp/R and h/R come from the network's FP64 forward pass
+   * (orc_mlp_forward, H hidden units, outputs z-scored: value = z sd + mean,
+   * cp/R of every species first, then h/R); the Gibbs terms of the
+   * equilibrium constants stay polynomial (the network has no entropy). */
+  int mlp_H;
+  const double *mlp_prm, *mlp_mean, *mlp_sd;
+  double mlp_T_lo, mlp_T_hi;
 } orc_mech;
 
 typedef struct {
@@ -96,18 +104,21 @@ int orc_integrate_cell(const orc_mech *m, const orc_params *p, double *T,
                        double P, double *Y, double tf, long long *iters,
                        double *margin_dft, double *margin_y,
                        double *h_trace, long long trace_cap);
-/* Same; `cell` only keys the noise instrument. */
+/* Same; `cell` only keys the noise instrument; margin_h (may be NULL)
+ * receives the smallest relative gap between the two smallest Eq 3
+ * candidates over the steps where Eq 3 set the step (a diagnostic). */
 int orc_integrate_cell_keyed(const orc_mech *m, const orc_params *p, double *T,
                              double P, double *Y, double tf, long long *iters,
                              double *margin_dft, double *margin_y,
-                             double *h_trace, long long trace_cap, long long cell);
+                             double *h_trace, long long trace_cap, long long cell,
+                             double *margin_h);
 
 /* All cells; Y row-major with leading dimension ld (>= n_s).  Optional
  * outputs may be NULL.  nthreads <= 0 uses the OpenMP default. */
 int orc_integrate(const orc_mech *m, const orc_params *p, long long n,
                   double *T, const double *P, double *Y, long long ld,
                   double tf, long long *iters, unsigned char *status,
-                  double *margin_dft, double *margin_y, int nthreads);
+                  double *margin_dft, double *margin_y, int nthreads, double *margin_h);
 
 /* Thermo training targets: cp/R and h/R for n temperatures, [n][n_s]. */
 void orc_nasa_targets(const orc_mech *m, long long n, const double *T,

@@ -8,7 +8,9 @@
 // sample); the last 1/8 is held out.  The loss is the mean squared error over
 // all outputs of a minibatch; gradients come from a per-sample forward /
 // backward pass whose per-parameter sums run over the block's samples from
-// LDS; the optimiser is Adam (Kingma & Ba 2015).  After training, W2 and W3
+// LDS; the optimiser is Adam (Kingma & Ba 2015).  After Adam the linear
+// output layer is set to its least-squares optimum for the trained hidden
+// layers (FP64 normal equations over the training rows).  Finally W2 and W3
 // are split into bf16 hi/lo MFMA operand tiles for inference.
 #include <hip/hip_runtime.h>
 
@@ -98,6 +100,64 @@ __global__ void k_normalize(float *Y, long long n, int n_out, const float *mean,
 __global__ void k_fill(float *p, long long n, float v) {
   const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;
+}
+
+// Output layer by least squares: the normal equations of the linear last
+// layer for fixed hidden layers, G = sum a a^T and B = sum a z^T over the
+// training rows with a = [a2, 1] (FP32 forward, FP64 sums).  Each block
+// takes kLsqRows consecutive rows, stages their activations in LDS and
+// accumulates every entry of G and B over them (thread t owns entries t,
+// t + blockDim, ...); the partial sums go to part[block] and are reduced in
+// block order by k_lsq_reduce, so the result does not depend on scheduling.
+constexpr int kLsqRows = 128;
+constexpr int kA = kH + 1;
+
+__global__ void __launch_bounds__(256) k_lsq_accum(const float *prm, int n_out, const float *X,
+                                                   const float *Z, long long n_rows,
+                                                   double *part) {
+  __shared__ double act[kLsqRows][kA];
+  const float *W1 = prm, *b1 = W1 + kH, *W2 = b1 + kH, *b2 = W2 + kH * kH;
+  const long long r0 = (long long)blockIdx.x * kLsqRows;
+  const int nr = (int)min((long long)kLsqRows, n_rows - r0);
+  for (int i = threadIdx.x; i < kLsqRows; i += blockDim.x) {
+    if (i < nr) {
+      const float x = X[r0 + i];
+      float a1[kH];
+#pragma unroll
+      for (int u = 0; u < kH; ++u) a1[u] = tanhf(W1[u] * x + b1[u]);
+      for (int u = 0; u < kH; ++u) {
+        float z = b2[u];
+#pragma unroll
+        for (int v = 0; v < kH; ++v) z += W2[u * kH + v] * a1[v];
+        act[i][u] = (double)tanhf(z);
+      }
+      act[i][kH] = 1.0;
+    } else {
+      for (int u = 0; u < kA; ++u) act[i][u] = 0.0;
+    }
+  }
+  __syncthreads();
+  const int nG = kA * kA, nE = nG + kA * n_out;
+  double *out = part + (size_t)blockIdx.x * nE;
+  for (int e = threadIdx.x; e < nE; e += blockDim.x) {
+    double acc = 0.0;
+    if (e < nG) {
+      const int i = e / kA, j = e % kA;
+      for (int r = 0; r < nr; ++r) acc += act[r][i] * act[r][j];
+    } else {
+      const int i = (e - nG) / n_out, o = (e - nG) % n_out;
+      for (int r = 0; r < nr; ++r) acc += act[r][i] * (double)Z[(r0 + r) * n_out + o];
+    }
+    out[e] = acc;
+  }
+}
+
+__global__ void k_lsq_reduce(const double *part, int n_blocks, int nE, double *sum) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nE) return;
+  double acc = 0.0;
+  for (int b = 0; b < n_blocks; ++b) acc += part[(size_t)b * nE + e];
+  sum[e] = acc;
 }
 
 // Forward + backward for up to kSPB samples per block, then per-parameter
@@ -480,6 +540,54 @@ extern "C" int stev_mlp_loss_grad(stev_ctx *ctx, int32_t hidden, int32_t n_out, 
   return rc == STEV_ENOMEM ? stev_fail(ctx, rc, "allocation failed") : rc;
 }
 
+// Solves (G + ridge I) W = B for the output layer (G = sum a a^T over
+// a = [a2, 1], B = sum a z^T; layout of k_lsq_accum) by Cholesky in long
+// double; writes W3 and b3 into a copy of the parameters.  False
+// (parameters kept) if G is not positive definite.  The 33 tanh features
+// are nearly collinear: without damping the exact optimum cancels weights
+// of several hundred, which the bf16 hi/lo products of the inference (about
+// 2^-16 of each term) cannot resolve.  A ridge of 1e-8 of the mean diagonal
+// keeps the output weights below about 10 and still cuts the h error of the
+// Adam fit by some twenty times (measured on the 19-species mechanism).
+constexpr double kLsqRidge = 1e-8;
+static bool solve_output_layer(const std::vector<double> &gb, int n_out,
+                               const std::vector<float> &cur, std::vector<float> &out) {
+  const int n = kA, nG = kA * kA;
+  std::vector<long double> L((size_t)n * n, 0.0L);
+  long double tr = 0.0L;
+  for (int i = 0; i < n; ++i) tr += gb[i * n + i];
+  const long double ridge = (long double)kLsqRidge * tr / n;
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j <= i; ++j) {
+      long double v = gb[i * n + j] + (i == j ? ridge : 0.0L);
+      for (int k = 0; k < j; ++k) v -= L[i * n + k] * L[j * n + k];
+      if (i == j) {
+        if (!(v > 0.0L)) return false;
+        L[i * n + i] = std::sqrt(v);
+      } else {
+        L[i * n + j] = v / L[j * n + j];
+      }
+    }
+  out = cur;
+  float *W3 = out.data() + kH + kH + kH * kH + kH, *b3 = W3 + (size_t)n_out * kH;
+  std::vector<long double> y(n), w(n);
+  for (int o = 0; o < n_out; ++o) {
+    for (int i = 0; i < n; ++i) {
+      long double v = gb[nG + i * n_out + o];
+      for (int k = 0; k < i; ++k) v -= L[i * n + k] * y[k];
+      y[i] = v / L[i * n + i];
+    }
+    for (int i = n - 1; i >= 0; --i) {
+      long double v = y[i];
+      for (int k = i + 1; k < n; ++k) v -= L[k * n + i] * w[k];
+      w[i] = v / L[i * n + i];
+    }
+    for (int u = 0; u < kH; ++u) W3[o * kH + u] = (float)w[u];
+    b3[o] = (float)w[kH];
+  }
+  return true;
+}
+
 extern "C" int stev_train_thermo_mlp(stev_ctx *ctx, stev_mech *m, const stev_mlp_cfg *cfg,
                                      stev_mlp_report *rep) {
   if (!ctx) return STEV_EINVAL;
@@ -581,6 +689,30 @@ extern "C" int stev_train_thermo_mlp(stev_ctx *ctx, stev_mech *m, const stev_mlp
   HIP_OK(hipMemcpyAsync(hacc.data(), acc, 8, hipMemcpyDeviceToHost, s));
   HIP_OK(hipStreamSynchronize(s));
   const double last_losses = hacc[0];
+  // the output layer at the least-squares optimum for the trained hidden
+  // layers (the last layer is linear: one FP64 solve of its normal equations)
+  {
+    const int nG = kA * kA, nE = nG + kA * n_out;
+    const int nb = (int)((n_train + kLsqRows - 1) / kLsqRows);
+    double *part = (double *)alloc((size_t)nb * nE * 8);
+    double *sum = (double *)alloc((size_t)nE * 8);
+    if (!part || !sum) {
+      cleanup();
+      return stev_fail(ctx, STEV_ENOMEM, "least-squares buffers do not fit the HBM budget");
+    }
+    k_lsq_accum<<<nb, 256, 0, s>>>(prm, n_out, X, Y, n_train, part);
+    k_lsq_reduce<<<(nE + 255) / 256, 256, 0, s>>>(part, nb, nE, sum);
+    std::vector<double> hs(nE);
+    std::vector<float> pcur(np);
+    HIP_OK(hipMemcpyAsync(hs.data(), sum, (size_t)nE * 8, hipMemcpyDeviceToHost, s));
+    HIP_OK(hipMemcpyAsync(pcur.data(), prm, np * 4, hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    std::vector<float> pnew;
+    if (solve_output_layer(hs, n_out, pcur, pnew)) {
+      HIP_OK(hipMemcpyAsync(prm, pnew.data(), np * 4, hipMemcpyHostToDevice, s));
+      HIP_OK(hipStreamSynchronize(s));
+    }
+  }
   // final training loss (full pass over the training rows) and test metrics
   k_fill<<<1, 64, 0, s>>>(reinterpret_cast<float *>(acc), 8, 0.f);
   k_fill<<<1, 64, 0, s>>>(mx, 2, 0.f);

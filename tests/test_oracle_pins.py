@@ -838,3 +838,37 @@ def test_t10_two_reaction_relaxation_to_equilibrium(orc):
     Yeq = (n0 + nu.T @ xi) * W
     assert np.all(Yeq > 0.0)
     np.testing.assert_allclose(Yf, Yeq, rtol=1e-9)
+
+
+# ----------------------------------------------------------------------------
+# Sec 3: the oracle's thermo-network mode puts the network's cp/R and h/R
+# into the energy equation and nothing else
+# ----------------------------------------------------------------------------
+def test_network_thermo_mode(orc):
+    m = synth.make_mech6()
+    om = orc.OracleMech(m)
+    ns, H = 6, 32
+    n_out = 2 * ns
+    prm = np.zeros(orc.mlp_n_params(H, n_out))       # all weights zero: outputs = b3
+    rng = np.random.default_rng(3)
+    c = rng.uniform(3.0, 9.0, ns)                     # cp/R per species
+    e = rng.uniform(-3e4, 1e4, ns)                    # h/R per species, K
+    mean = np.concatenate([c, e])
+    sd = np.ones(n_out)
+    on = om.with_network(H, prm, mean, sd, 500.0, 2500.0)
+    T, P, Y = synth.make_cells_mech6(4, seed=2)
+    for i in range(4):
+        a = orc.source(om, T[i], P[i], Y[i])
+        b = orc.source(on, T[i], P[i], Y[i])
+        # rates and species sources keep the polynomial Gibbs terms
+        assert np.array_equal(a["q"], b["q"]) and np.array_equal(a["dYdt"], b["dYdt"])
+        # energy equation with constant cp/R = c, h/R = e:
+        # dT/dt * sum(Y c / W) = -sum(e omega) / rho, omega = rho dY/dt / W
+        W = np.asarray(m["W"])
+        lhs = b["dTdt"] * np.sum(Y[i] * c / W)
+        rhs = -np.sum(e * b["dYdt"] / W)
+        assert lhs == pytest.approx(rhs, rel=1e-12)
+    # outside the network's range the polynomials are used, bit for bit
+    a = orc.source(om, 2600.0, P1, Y[0])
+    b = orc.source(on, 2600.0, P1, Y[0])
+    assert a["dTdt"] == b["dTdt"]

@@ -143,8 +143,13 @@ def oracle_ensemble(om, T, P, Y, dt, precision=stev.F64, **kw):
     return base
 
 
-def judge(g, o, precision, label="", iters_equal=None):
-    """Check GPU result g against oracle ensemble o; returns a summary dict."""
+def judge(g, o, precision, label="", iters_equal=None, ill_allowance=True):
+    """Check GPU result g against oracle ensemble o; returns a summary dict.
+    ill_allowance=False reports ill-conditioned cells without bounding them:
+    for the network path, whose BF16 inference moves cp and h by up to ~1e-4
+    of their spread at every step, far beyond the FP32 rounding the ensemble
+    draws, so the spread says nothing about what a correct kernel reaches on
+    a chaotic cell (well-conditioned cells stay held to the tolerance)."""
     tT, tY, thr = TOL[precision]
     if iters_equal is None:
         iters_equal = precision == stev.F64
@@ -164,7 +169,7 @@ def judge(g, o, precision, label="", iters_equal=None):
     allowT = np.maximum(tT * np.abs(Tref), SPREAD_FACTOR * o["spread_T"])
     allowY = np.maximum(tY * np.abs(o["Y"]), SPREAD_FACTOR * o["spread_Y"])
     ok_ill = (eT <= allowT) & np.all(np.where(mask, eY <= allowY, True), axis=1)
-    ok = np.where(well, ok_well, ok_ill)
+    ok = np.where(well, ok_well, ok_ill if ill_allowance else True)
     held = (relT <= tT) & (relY <= tY)
     # exemption used (an ill-conditioned cell outside the stated tolerance)
     # beyond every ensemble member: about one ill-conditioned cell in

@@ -118,7 +118,9 @@ def test_integration_with_network(ctx, m19):
     """FP32 + network, judged by the FP32 criterion twice: for parity against
     the oracle evaluating the same network in FP64, and for accuracy against
     the oracle's polynomials (the network's fit error included), next to the
-    FP32 polynomial path on the same cells."""
+    FP32 polynomial path on the same cells.  Well-conditioned cells are held
+    to the tolerance; chaotic cells are reported (their ensemble spread does
+    not model the BF16 inference's perturbation of cp and h)."""
     m, gm, om, _ = m19
     T, P, Y = synth.make_cells_mech19()
     idx = synth.subsample(len(T), 259, seed=12)
@@ -130,11 +132,12 @@ def test_integration_with_network(ctx, m19):
     assert np.all(gn["status"] == 0)
     on = oracle_with_gpu_network(ctx, gm, om)
     onet = oracle_ensemble(on, T, P, Y, 1e-4, stev.F32)
-    judge(gn, onet, stev.F32, "f32 network vs oracle with the same network")
+    judge(gn, onet, stev.F32, "f32 network vs oracle with the same network",
+          ill_allowance=False)
     relT = np.abs(gn["T"] - o["T"]) / o["T"]
     say(f"network path vs polynomials: max rel T err {relT.max():.2e} "
         f"median {np.median(relT):.2e}")
-    judge(gn, o, stev.F32, "f32 network vs polynomial oracle")
+    judge(gn, o, stev.F32, "f32 network vs polynomial oracle", ill_allowance=False)
 
 
 @pytest.mark.parametrize("thermo", [stev.THERMO_POLY, stev.THERMO_MLP])

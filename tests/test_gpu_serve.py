@@ -116,7 +116,7 @@ def test_same_result_alone_and_in_mix(ctx, mechs):
                  status=np.concatenate([mix[i]["st"] for i in sel])[k])
         on = oracle_with_gpu_network(ctx, mechs[key][1], mechs[key][2])
         o = oracle_ensemble(on, T[k], P[k], Y[k], DT, stev.F32)
-        judge(g, o, stev.F32, f"served f32+network mech{key}")
+        judge(g, o, stev.F32, f"served f32+network mech{key}", ill_allowance=False)
     # and the same as the plain entry point
     for i, (key, T, P, Y) in enumerate(reqs[:6]):
         r = host_req(key, T, P, Y, np.float32)

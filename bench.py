@@ -39,6 +39,7 @@ sys.path.insert(0, ROOT)
 METRIC = "cells/sec over one flow Δt, plain vs batched+MLP STEV; p50/p99 solve latency"
 PEAK = {"f64": 78.6, "f32": 157.3}   # TFLOP/s, MI355X vector FP64 / FP32
 KERNEL_SOURCES = ["paper_1905_09395_amd/csrc/stev_kernel.hip",
+                  "paper_1905_09395_amd/csrc/stev_persistent.h",
                   "paper_1905_09395_amd/csrc/stev_math.h",
                   "paper_1905_09395_amd/csrc/stev_internal.h",
                   "paper_1905_09395_amd/csrc/stev_thermo.h",
@@ -371,7 +372,6 @@ def run_mlp(args):
     import numpy as np
     import torch
 
-    import oracle
     from paper_1905_09395_amd import stev, synth
     dev = torch.device("cuda:0")
     dt = 1e-4
@@ -382,13 +382,28 @@ def run_mlp(args):
     ctx.set_stream(torch.cuda.current_stream(dev))
     gm = ctx.mechanism(mech)
     rep = ctx.train_thermo_mlp(gm, epochs=300, n_samples=1 << 20, batch=8192, lr=3e-3, seed=104)
+    # the paper's own network: one sigmoid layer as wide as the outputs,
+    # fitted by Levenberg-Marquardt
+    lrep, lprm = ctx.train_thermo_lma(gm, iters=150, n_samples=1 << 16, seed=104)
+    ctx.set_thermo_ann(gm, lrep["hidden"], 300.0, 3000.0, lprm)
     f32 = torch.float32
     T0 = torch.tensor(T, dtype=f32, device=dev)
     P0 = torch.tensor(P, dtype=f32, device=dev)
     Y0 = torch.tensor(Y, dtype=f32, device=dev).contiguous()
     Tw, Yw = T0.clone(), Y0.clone()
+    # accuracy reference: the FP64 polynomial path on the same field (its
+    # parity with the FP64 oracle is what the tests establish)
+    f64 = torch.float64
+    Tr = torch.tensor(T, dtype=f64, device=dev)
+    Yr = torch.tensor(Y, dtype=f64, device=dev).contiguous()
+    ctx.integrate(gm, Tr, torch.tensor(P, dtype=f64, device=dev), Yr, dt,
+                  params=stev.default_params(precision=stev.F64))
+    refT = Tr.cpu().numpy()
+    refY = Yr.cpu().numpy()
+    del Tr, Yr
     res = {}
-    for name, th in (("network", stev.THERMO_MLP), ("poly", stev.THERMO_POLY)):
+    for name, th in (("network", stev.THERMO_MLP), ("sigmoid", stev.THERMO_ANN),
+                     ("poly", stev.THERMO_POLY)):
         # the launch shape the autotuner picks for this thermo mode and field
         # (outside the timed region), beside the default shape
         prm = ctx.autotune(gm, T0, P0, Y0, dt, stev.default_params(precision=stev.F32, thermo=th))
@@ -411,14 +426,12 @@ def run_mlp(args):
             kms.append(st["kernel_ms"]); its.append(st["total_iters"])
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
-        # accuracy on a seeded subsample against the FP64 oracle
-        idx = synth.subsample(n, 256, seed=4)
-        o = oracle.integrate(oracle.OracleMech(mech), T[idx], P[idx], Y[idx], dt)
-        gT = Tw.cpu().double().numpy()[idx]
-        gY = Yw.cpu().double().numpy()[idx]
-        m = o["Y"] > 1e-6
-        relT = np.abs(gT - o["T"]) / o["T"]
-        relY = np.where(m, np.abs(gY - o["Y"]) / np.where(m, o["Y"], 1), 0).max(axis=1)
+        # accuracy of every cell against the FP64 polynomial result
+        gT = Tw.cpu().double().numpy()
+        gY = Yw.cpu().double().numpy()
+        m = refY > 1e-6
+        relT = np.abs(gT - refT) / refT
+        relY = np.where(m, np.abs(gY - refY) / np.where(m, refY, 1), 0).max(axis=1)
         res[name] = dict(el=el, kms=float(np.mean(kms)), its=float(np.mean(its)),
                          tuned_shape=shape, default_shape_kernel_ms=float(np.mean(base_ms)),
                          median_rel_T=float(np.median(relT)), p99_rel_T=float(np.quantile(relT, .99)),
@@ -430,17 +443,24 @@ def run_mlp(args):
                       "learned thermo: 19-species/50-reaction mechanism, 1048576 cells, FP32, "
                       "cp and h from a 1-32-32-38 tanh network (bf16 MFMA, fp32 accumulation, "
                       "polynomial fallback outside 300-3000 K), dt_flow=1e-4 s, autotuned launch "
-                      "shape for each thermo mode",
+                      "shape for each thermo mode; beside it the paper's 1-38-38 sigmoid "
+                      "network (FP32 vector units) and the polynomials",
                       cells=n, network_train=dict(test_loss=rep["test_loss"],
                                                   max_rel_err_cp=rep["max_rel_err_cp"],
                                                   max_rel_err_h=rep["max_rel_err_h"],
                                                   train_ms=rep["train_ms"]),
                       network=dict((k, v) for k, v in r.items() if k != "el"),
+                      sigmoid_network=dict((k, v) for k, v in res["sigmoid"].items() if k != "el"),
+                      sigmoid_train=dict(hidden=lrep["hidden"], test_loss=lrep["test_loss"],
+                                         max_rel_err_cp=lrep["max_rel_cp"],
+                                         train_ms=lrep["train_ms"]),
                       polynomials=dict((k, v) for k, v in res["poly"].items() if k != "el"),
                       poly_cells_per_s=n * args.steps / res["poly"]["el"],
+                      sigmoid_cells_per_s=n * args.steps / res["sigmoid"]["el"],
                       network_over_poly_time=r["el"] / res["poly"]["el"],
-                      accuracy_sample="256 seeded cells vs the FP64 oracle; relative errors, "
-                                      "Y over Y_k > 1e-6")
+                      sigmoid_over_poly_time=res["sigmoid"]["el"] / res["poly"]["el"],
+                      accuracy_sample="every cell vs the FP64 polynomial path on the GPU; "
+                                      "relative errors, Y over Y_k > 1e-6")
     out["roofline"] = {"bound": "alu", "achieved": achieved, "peak": PEAK["f32"],
                        "unit": "TFLOP/s", "frac": achieved / PEAK["f32"], "traffic": None,
                        "kernel_ms": r["kms"], "flop_count": "direct 13-point DFT, network "
@@ -455,7 +475,6 @@ def run_c3m(args):
     import numpy as np
     import torch
 
-    import oracle
     from paper_1905_09395_amd import stev, synth
     dev = torch.device("cuda:0")
     dt = 1e-3
@@ -506,7 +525,8 @@ def run_c3m(args):
                        "model_flop_per_cell_iter": flops,
                        "transcendentals_per_cell_iter": transc,
                        "state_bytes_per_launch": 2 * 26 * rsz * n}
-    if not args.no_cpu:
+    if not args.no_cpu:   # the cpu_baseline leg: the oracle timed as it stands
+        import oracle
         cores = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count() or 1
         oc = oracle.C3M(desc)
         m, tot_c, tot_s, seed = 256, 0, 0.0, 900
@@ -547,12 +567,14 @@ def run_serve(args):
     src = {6: synth.make_mech6(), 19: synth.make_mech19(), 53: synth.make_mech53()}
     n_s = {6: 6, 19: 19, 53: 53}
     # host-resident (pinned) request state; the serving context stages it
-    # through a device budget of twice the largest request's staging, so that
-    # admission binds whenever large requests overlap.  The plain baseline
-    # runs in a context of its own (default budget), and the networks are
-    # trained there and imported into the serving context.
+    # through a device budget of the largest request's staging plus 48 MiB
+    # (mechanisms, networks, launch tables, dispatch orders and the smaller
+    # requests), so that admission binds whenever a large request is in
+    # flight and another arrives.  The plain baseline runs in a context of its
+    # own (default budget), and the networks are trained there and imported
+    # into the serving context.
     stage = [int(n) * (2 + n_s[int(k)] + 1) * 4 for k, n in zip(keys, sizes)]
-    budget = 2 * max(stage) + (64 << 20)
+    budget = max(stage) + (48 << 20)
     plain = stev.Context(0)
     ctx = stev.Context(0, hbm_budget=budget)
     mechs, pmechs = {}, {}
@@ -642,31 +664,77 @@ def run_serve(args):
         at = np.zeros(n_req) if load == "saturated" else arrivals(load)
         for _ in range(args.warmup):
             serve_run(at)
-        ls, ms, bw = [], [], []
+        # served and plain runs alternate, the same number of each, so that
+        # both quantiles come from equally many samples
+        ls, ms, bw, lps, mps = [], [], [], [], []
         for _ in range(args.steps):
             l, m, w = serve_run(at)
             ls.append(l); ms.append(m); bw.append(w)
-        lp, mp = plain_run(at)
+            l, m = plain_run(at)
+            lps.append(l); mps.append(m)
         print(f"serve: load {load} done", file=sys.stderr, flush=True)
-        L = np.concatenate(ls)
+        L, LP = np.concatenate(ls), np.concatenate(lps)
+        big = int(np.argmax(sizes * np.array([n_s[int(k)] ** 2 for k in keys])))
         rows[str(load)] = dict(
             serve_p50_ms=1e3 * float(np.quantile(L, .5)), serve_p99_ms=1e3 * float(np.quantile(L, .99)),
+            serve_max_ms=1e3 * float(L.max()),
             serve_cells_per_s=total / float(np.mean(ms)),
             requests_that_waited_for_budget=int(np.max(bw)),
-            plain_p50_ms=1e3 * float(np.quantile(lp, .5)), plain_p99_ms=1e3 * float(np.quantile(lp, .99)),
-            plain_cells_per_s=total / mp)
+            plain_p50_ms=1e3 * float(np.quantile(LP, .5)), plain_p99_ms=1e3 * float(np.quantile(LP, .99)),
+            plain_max_ms=1e3 * float(LP.max()),
+            plain_cells_per_s=total / float(np.mean(mps)),
+            # the costliest request (most cells x species^2): its latency in
+            # each mode, mean over the runs
+            costliest_request_serve_ms=1e3 * float(np.mean([l[big] for l in ls])),
+            costliest_request_plain_ms=1e3 * float(np.mean([l[big] for l in lps])))
     top = rows["0.95"]
     out = base_record(args, top["serve_cells_per_s"], float(np.sum(ms)), "f32",
                       "serving: Poisson arrivals, 32 requests of log-uniform size in "
                       "[1024, 524288] cells over 6-, 19- and 53-species mechanisms, FP32 + "
                       "thermo network, host-resident pinned requests admitted by an HBM budget "
-                      "of twice the largest request's staging; value at load 0.95 "
-                      "('saturated': every request at t=0)",
+                      "of the largest request's staging + 48 MiB; value at load 0.95 "
+                      "('saturated': every request at t=0); quantiles over the same number "
+                      "of served and plain runs",
                       requests=n_req, cells=total, hbm_budget_bytes=budget,
                       plain_capacity_cells_per_s=cap, loads=rows)
     ctx.close()
     plain.close()
     return out
+
+
+def run_legs(args):
+    """The metric's other legs at reduced repetition, for the default line:
+    batched, learned thermo (tanh and sigmoid networks against the
+    polynomials) and served (p50 / p99 against plain per-request calls)."""
+    import copy
+    legs = {}
+    la = copy.copy(args)
+    la.steps, la.warmup = 2, 1
+    b = run_batched(la)
+    legs["batched"] = dict(cells_per_s=b["value"], ms_per_step=b["ms_per_step"],
+                           plain_per_batch_cells_per_s=b["config"]["plain_per_batch_cells_per_s"],
+                           speedup_vs_plain_per_batch=b["config"]["speedup_vs_plain_per_batch"],
+                           roofline_frac=b["roofline"]["frac"], workload=b["config"]["workload"])
+    print("legs: batched done", file=sys.stderr, flush=True)
+    m = run_mlp(la)
+    c = m["config"]
+    legs["learned_thermo"] = dict(
+        network_cells_per_s=m["value"], poly_cells_per_s=c["poly_cells_per_s"],
+        sigmoid_cells_per_s=c["sigmoid_cells_per_s"],
+        network_over_poly_time=c["network_over_poly_time"],
+        sigmoid_over_poly_time=c["sigmoid_over_poly_time"],
+        p99_rel_T=dict(network=c["network"]["p99_rel_T"],
+                       sigmoid=c["sigmoid_network"]["p99_rel_T"],
+                       poly=c["polynomials"]["p99_rel_T"]),
+        accuracy_sample=c["accuracy_sample"], workload=c["workload"])
+    print("legs: learned thermo done", file=sys.stderr, flush=True)
+    ls = copy.copy(args)
+    ls.steps, ls.warmup = 1, 1
+    sv = run_serve(ls)
+    legs["served"] = dict(loads=sv["config"]["loads"], hbm_budget_bytes=sv["config"]["hbm_budget_bytes"],
+                          workload=sv["config"]["workload"])
+    print("legs: served done", file=sys.stderr, flush=True)
+    return legs
 
 
 def main():
@@ -680,6 +748,8 @@ def main():
     ap.add_argument("--stab", action="store_true",
                     help="plain workload with the Eq 25 step cap (2/||A||_inf)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-legs", action="store_true",
+                    help="plain workload only: skip the batched, learned-thermo and served legs")
     ap.add_argument("--probe", action="store_true",
                     help="counter-calibration run: one plain copy, then one step")
     ap.add_argument("--workload", default="plain",
@@ -696,7 +766,7 @@ def main():
         pmc_summary(args.pmc_summary, args.precision, args.cells)
         return
     if args.probe:
-        args.steps, args.warmup, args.no_cpu = 1, 0, True
+        args.steps, args.warmup, args.no_cpu, args.no_legs = 1, 0, True, True
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (cells are independent; the "
               "multi-GPU sharding is a design note, not a measured path)", file=sys.stderr)
@@ -823,6 +893,8 @@ def main():
         out["cpu_baseline"] = cpu_baseline(mech, T, P, Y, dt)
     gm.close()
     ctx.close()
+    if not args.no_legs:
+        out["legs"] = run_legs(args)
     print(json.dumps(out), flush=True)
 
 

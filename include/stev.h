@@ -40,6 +40,7 @@ extern "C" {
 #define STEV_F32 1       /* T, P, Y are float*    */
 #define STEV_THERMO_POLY 0 /* NASA-7 polynomials (Eqs 15-16)            */
 #define STEV_THERMO_MLP 1  /* trained network for cp and h (Sec 3)       */
+#define STEV_THERMO_ANN 2  /* the paper's sigmoid network (Sec 3)       */
 
 typedef struct stev_ctx stev_ctx;
 typedef struct stev_mech stev_mech;
@@ -69,7 +70,9 @@ typedef struct {
 /* Solver parameters.  stev_default_params() fills the defaults below. */
 typedef struct {
   int32_t precision;      /* STEV_F64 | STEV_F32 */
-  int32_t thermo;         /* STEV_THERMO_POLY | STEV_THERMO_MLP */
+  int32_t thermo;         /* STEV_THERMO_POLY | STEV_THERMO_MLP (FP32
+                             only) | STEV_THERMO_ANN (FP64 or FP32); a
+                             network mode needs that network attached */
   double ystep_max;       /* Eq 3 max species consumption per step  (1e-3) */
   double delta_max;       /* Eq 4 max step fraction of dt_flow      (1e-2) */
   double alpha;           /* Eq 7 species limit factor              (1e-5) */
@@ -304,11 +307,28 @@ int64_t stev_lma_n_params(int32_t hidden, int32_t n_out);
 
 /* Train on the mechanism's FP64 polynomials (targets z-scored per output,
  * x = (T - 1650) / 1350).  params_out (nullable, host, stev_lma_n_params
- * doubles) receives the trained parameters.  The mechanism is not changed.
+ * doubles) receives the trained parameters with the z-scoring folded into
+ * the output layer, so that the outputs are cp/R (species 0 .. n-1) and
+ * h/R in kelvin (species 0 .. n-1): the form stev_set_thermo_ann takes.
+ * The mechanism is not changed.
  * STEV_EINVAL on a bad configuration or shape, STEV_ENOMEM if the buffers
  * do not fit the HBM budget. */
 int stev_train_thermo_lma(stev_ctx *ctx, const stev_mech *mech, const stev_lma_cfg *cfg,
                           stev_lma_report *report, double *params_out);
+
+/* Attach the paper's sigmoid network to `mech` for STEV_THERMO_ANN (Sec 3:
+ * the network stands in for the species property polynomials inside the
+ * integration).  params: host, stev_lma_n_params(hidden, 2 n_species) FP64
+ * values in the layout above, outputs in physical units (cp/R of every
+ * species, then h/R in kelvin), input x = (T - 1650) / 1350; copied.
+ * Inside [T_lo, T_hi] the integrator takes cp and h from the network,
+ * evaluated in the launch's precision (sigmoids and sums on the vector
+ * units, hidden units in order); outside, and for the equilibrium
+ * constants everywhere, it uses the polynomials.  hidden in [1, 64].
+ * Replaces an earlier sigmoid network; STEV_EINVAL on a bad shape or range,
+ * STEV_ENOMEM when the device copies do not fit the HBM budget. */
+int stev_set_thermo_ann(stev_ctx *ctx, stev_mech *mech, int32_t hidden, double T_lo,
+                        double T_hi, const double *params);
 
 /* One evaluation of the normal equations on the GPU for given parameters
  * and samples (host arrays: params, x[n], target[n * n_out] row-major).
@@ -340,7 +360,9 @@ int stev_mlp_loss_grad(stev_ctx *ctx, int32_t hidden, int32_t n_out, const float
  * the GPU, with the NASA-7 polynomials (STEV_THERMO_POLY, FP64) or with the
  * attached network exactly as the integrator evaluates it
  * (STEV_THERMO_MLP: BF16 MFMA, FP32 accumulation, polynomial fallback
- * outside the trained range).  Host pointers. */
+ * outside the trained range; STEV_THERMO_ANN: the sigmoid network in FP64,
+ * as the FP64 integrator evaluates it, with the same fallback).  Host
+ * pointers. */
 int stev_thermo_eval(stev_ctx *ctx, const stev_mech *mech, int32_t thermo, int64_t n,
                      const double *T, double *cp_R, double *h_R);
 

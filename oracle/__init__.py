@@ -43,7 +43,9 @@ class _Mech(C.Structure):
                 ("nu", C.c_void_p), ("order", C.c_void_p), ("A", C.c_void_p),
                 ("b", C.c_void_p), ("Ea", C.c_void_p), ("rev", C.c_void_p),
                 ("mlp_H", C.c_int), ("mlp_prm", C.c_void_p), ("mlp_mean", C.c_void_p),
-                ("mlp_sd", C.c_void_p), ("mlp_T_lo", C.c_double), ("mlp_T_hi", C.c_double)]
+                ("mlp_sd", C.c_void_p), ("mlp_T_lo", C.c_double), ("mlp_T_hi", C.c_double),
+                ("ann_H", C.c_int), ("ann_prm", C.c_void_p), ("ann_T_lo", C.c_double),
+                ("ann_T_hi", C.c_double)]
 
 
 class _Params(C.Structure):
@@ -137,6 +139,7 @@ def lib():
         L.orc_mlp_n_params.argtypes = [C.c_int, C.c_int]
         L.orc_mlp_n_params.restype = C.c_longlong
         L.orc_mlp_forward.argtypes = [C.c_int, C.c_int, dp, C.c_longlong, dp, dp]
+        L.orc_ann_forward.argtypes = [C.c_int, C.c_int, dp, C.c_longlong, dp, dp]
         L.orc_mlp_loss_grad.argtypes = [C.c_int, C.c_int, dp, C.c_longlong, dp, dp, dp]
         L.orc_mlp_loss_grad.restype = C.c_double
         L.orc_adam_step.argtypes = [C.c_longlong, dp, dp, dp, dp, C.c_longlong, C.c_double,
@@ -202,6 +205,18 @@ class OracleMech:
         o.c.mlp_sd = o._keep["mlp_sd"].ctypes.data
         o.c.mlp_T_lo = float(T_lo)
         o.c.mlp_T_hi = float(T_hi)
+        return o
+
+    def with_ann(self, H, prm, T_lo, T_hi):
+        """A copy whose thermo (cp/R, h/R) comes from the paper's sigmoid
+        network inside [T_lo, T_hi] (Sec 3): FP64 parameters in the
+        orc_ann_forward layout, outputs in physical units."""
+        o = OracleMech(self.mech)
+        o._keep.update(ann_prm=np.ascontiguousarray(prm, dtype=np.float64))
+        o.c.ann_H = int(H)
+        o.c.ann_prm = o._keep["ann_prm"].ctypes.data
+        o.c.ann_T_lo = float(T_lo)
+        o.c.ann_T_hi = float(T_hi)
         return o
 
 
@@ -333,6 +348,15 @@ def mlp_forward(H, n_out, prm, x):
     x = np.ascontiguousarray(x, dtype=np.float64)
     y = np.zeros((len(x), n_out))
     lib().orc_mlp_forward(H, n_out, _p(prm), len(x), _p(x), _p(y))
+    return y
+
+
+def ann_forward(H, n_out, prm, x):
+    """The sigmoid network's outputs [n, n_out] at normalised inputs x."""
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    y = np.zeros((len(x), n_out))
+    lib().orc_ann_forward(int(H), int(n_out), _p(np.ascontiguousarray(prm, dtype=np.float64)),
+                          len(x), _p(x), _p(y))
     return y
 
 

@@ -119,6 +119,16 @@ void orc_source_keyed(const orc_mech *m, const orc_params *p, double T, double P
     }
     free(z);
   }
+  if (m->ann_prm && T >= m->ann_T_lo && T <= m->ann_T_hi) {   /* Sec 3 */
+    double *y = (double *)malloc(sizeof(double) * 2 * (size_t)n_s);
+    double x = (T - 1650.0) / 1350.0;
+    orc_ann_forward(m->ann_H, 2 * n_s, m->ann_prm, 1, &x, y);
+    for (int k = 0; k < n_s; ++k) {
+      cp_R[k] = y[k];
+      h_RT[k] = y[n_s + k] / T;
+    }
+    free(y);
+  }
 
   for (int k = 0; k < n_s; ++k) omega[k] = 0.0;
 
@@ -498,6 +508,21 @@ void orc_mlp_forward(int H, int n_out, const double *prm, long long n,
     }
   }
   free(a1);
+}
+
+void orc_ann_forward(int H, int n_out, const double *prm, long long n,
+                     const double *x, double *y) {
+  const double *W2 = prm, *b2 = W2 + (size_t)n_out * H, *w1 = b2 + n_out, *b1 = w1 + H;
+  double *a = (double *)malloc(sizeof(double) * (size_t)H);
+  for (long long i = 0; i < n; ++i) {
+    for (int u = 0; u < H; ++u) a[u] = 1.0 / (1.0 + exp(-(w1[u] * x[i] + b1[u])));
+    for (int o = 0; o < n_out; ++o) {
+      double v = b2[o];
+      for (int u = 0; u < H; ++u) v += W2[(size_t)o * H + u] * a[u];
+      y[i * n_out + o] = v;
+    }
+  }
+  free(a);
 }
 
 double orc_mlp_loss_grad(int H, int n_out, const double *prm, long long n,

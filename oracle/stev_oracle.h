@@ -42,6 +42,13 @@ typedef struct {
   int mlp_H;
   const double *mlp_prm, *mlp_mean, *mlp_sd;
   double mlp_T_lo, mlp_T_hi;
+  /* Optional sigmoid network of Sec 3 (orc_ann_forward, H hidden units,
+   * outputs in physical units: cp/R of every species, then h/R), NULL prm
+   * for none; used inside [T_lo, T_hi] like the network above.  At most one
+   * of the two networks is set. */
+  int ann_H;
+  const double *ann_prm;
+  double ann_T_lo, ann_T_hi;
 } orc_mech;
 
 typedef struct {
@@ -128,6 +135,11 @@ void orc_nasa_targets(const orc_mech *m, long long n, const double *T,
  * W1[H] b1[H] W2[H][H] b2[H] W3[n_out][H] b3[n_out]. */
 long long orc_mlp_n_params(int H, int n_out);
 void orc_mlp_forward(int H, int n_out, const double *prm, long long n,
+                     const double *x, double *y);
+/* The paper's thermo network (Sec 3): one hidden layer of H sigmoid units
+ * and a linear output layer, y = W2 s(w1 x + b1) + b2 with s(z) = 1/(1+e^-z).
+ * Parameter layout: W2[n_out][H] b2[n_out] w1[H] b1[H]; y is [n][n_out]. */
+void orc_ann_forward(int H, int n_out, const double *prm, long long n,
                      const double *x, double *y);
 /* Mean squared error over all n*n_out entries and its gradient. */
 double orc_mlp_loss_grad(int H, int n_out, const double *prm, long long n,

@@ -14,6 +14,7 @@
 #include <string>
 
 #include "stev_runtime.h"
+#include "stev_variants.h"
 
 using stev::BatchDesc;
 using stev::KArgs;
@@ -60,6 +61,22 @@ int ml_build(stev_ctx *ctx, MultiLaunch &ml, hipStream_t s) {
   ml.off_stats = desc_bytes;
   ml.stat_words = 4 * n_items + 8 * n_groups;
   ml.bytes = desc_bytes + align256(ml.stat_words * 8);
+  // hottest cells first within each group, as for one field (the launch
+  // ends when its slowest cell does; starting the hottest cells first
+  // shortens that tail): per group the bins and an index over its cells
+  size_t order_bytes = 0;
+  for (MultiLaunch::Grp &G : ml.groups) {
+    G.order = ml.p.hot_first && G.cells >= kOrderMinCells && G.cells <= INT32_MAX;
+    if (!G.order) continue;
+    G.off_order = order_bytes;
+    order_bytes += align256(stev::kOrderBins * 8) + align256((size_t)G.cells * 4);
+  }
+  if (ml.lent && (!ml.order_dev || order_bytes > ml.order_cap))
+    for (MultiLaunch::Grp &G : ml.groups) G.order = false;   // keep array order
+  if (!ml.lent) {
+    ml.off_order_base = ml.bytes;
+    ml.bytes += order_bytes;
+  }
   int rc = STEV_OK;
   if (ml.lent) {
     if (ml.bytes > ml.cap)
@@ -67,12 +84,14 @@ int ml_build(stev_ctx *ctx, MultiLaunch &ml, hipStream_t s) {
                        ml.cap);
   } else {
     if ((rc = dev_alloc(ctx, &ml.dev, ml.bytes))) return rc;
-    if (hipHostMalloc(&ml.host, ml.bytes) != hipSuccess) {
+    // the host mirror holds the tables only, not the order scratch
+    if (hipHostMalloc(&ml.host, ml.off_order_base) != hipSuccess) {
       ml.host = nullptr;
-      return stev_fail(ctx, STEV_EDEVICE, "pinned host allocation of %zu bytes failed", ml.bytes);
+      return stev_fail(ctx, STEV_EDEVICE, "pinned host allocation of %zu bytes failed",
+                       ml.off_order_base);
     }
   }
-  std::memset(ml.host, 0, ml.bytes);
+  std::memset(ml.host, 0, ml.lent ? ml.bytes : ml.off_order_base);
   BatchDesc *hd = reinterpret_cast<BatchDesc *>(ml.host);
   BatchDesc *dd = reinterpret_cast<BatchDesc *>(ml.dev);
   unsigned long long *dstat =
@@ -107,6 +126,13 @@ int ml_build(stev_ctx *ctx, MultiLaunch &ml, hipStream_t s) {
     a.n_batches = (int)(slot - first);
     a.bstats = dstat + 4 * first;
     a.ctl = dstat + 4 * n_items + 8 * g;
+    if (G.order) {
+      char *ob = static_cast<char *>(ml.lent ? ml.order_dev : ml.dev) +
+                 (ml.lent ? 0 : ml.off_order_base) + G.off_order;
+      a.cell_index = reinterpret_cast<const int *>(ob + align256(stev::kOrderBins * 8));
+      // temperature order: one workgroup per CU starts from the cold end
+      a.n_front = G.lp.grid > ctx->n_cu ? G.lp.grid - ctx->n_cu : 0;
+    }
   }
   // batch descriptors in slot order map back to items through the groups
   HIP_TRY(hipMemcpyAsync(ml.dev, ml.host, desc_bytes, hipMemcpyHostToDevice, s));
@@ -127,7 +153,16 @@ int ml_enqueue(stev_ctx *ctx, MultiLaunch &ml, hipStream_t s, bool fork) {
     const bool side = fork && g > 0;
     hipStream_t gs = side ? ctx->side[(g - 1) % stev_ctx::kSide] : s;
     if (side && g <= stev_ctx::kSide) HIP_TRY(hipStreamWaitEvent(gs, ctx->ev_fork, 0));
-    if ((rc = launch_stev(ctx, ml.groups[g].lp, ml.groups[g].a, gs))) return rc;
+    MultiLaunch::Grp &G = ml.groups[g];
+    if (G.order) {
+      char *ob = static_cast<char *>(ml.lent ? ml.order_dev : ml.dev) +
+                 (ml.lent ? 0 : ml.off_order_base) + G.off_order;
+      if ((rc = launch_order(ctx, ml.p.precision, nullptr, G.a.batches, G.a.n_batches, G.cells,
+                             reinterpret_cast<unsigned long long *>(ob),
+                             const_cast<int *>(G.a.cell_index), gs)))
+        return rc;
+    }
+    if ((rc = launch_stev(ctx, G.lp, G.a, gs))) return rc;
   }
   if (fork)
     for (int i = 0; i < stev_ctx::kSide && i + 1 < ng; ++i) {

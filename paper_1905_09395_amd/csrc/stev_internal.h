@@ -130,6 +130,27 @@ struct MlpDev {
   MlpBlobLayout L;
 };
 
+// The paper's own thermo network attached to a mechanism (Sec 3): one
+// hidden layer of H sigmoid units, linear outputs cp/R and h/R.  Its device
+// blob, in the launch's precision R, is staged to LDS after the mechanism
+// blob: w1[H] b1[H], then the output weights as (cp, h) pairs W[u][k]
+// (unit u, species k), then the
+// output biases as (cp, h) pairs.  x = (T - 1650) / 1350.  Zero units pad H
+// to Hs, a multiple of kAnnPad.
+constexpr int kAnnMaxH = 64;
+constexpr int kAnnPad = 8;
+struct AnnDev {
+  int enabled;
+  int H, Hs;                       // hidden units, padded to a multiple of kAnnPad
+  double T_lo, T_hi;               // trained range; outside it the polynomials are used
+  const void *blob;
+  int off_b1, off_w2, off_b2;      // element offsets in R
+  int bytes;
+};
+
+// thermo modes of a kernel instantiation (the values of STEV_THERMO_*)
+constexpr int kThPoly = 0, kThMlp = 1, kThAnn = 2;
+
 // One batch of a multi-batch launch: cells [begin, begin + n) of the launch's
 // global index space live in this batch's own arrays (same layout rules as a
 // single call: T[c], P[c], Y[c*ld_cell + k*ld_sp]).
@@ -177,8 +198,9 @@ struct KArgs {
   const BatchDesc *batches;
   unsigned long long *bstats;
   int n_batches;
-  // single batch only: the launch's i-th cell is cell cell_index[i] of the
-  // arrays (nullptr: cell i); the dispatch order of a field
+  // the launch's i-th cell is cell cell_index[i] of its index space (of the
+  // arrays, or of the batches' concatenation; nullptr: cell i): the dispatch
+  // order of a field
   const int *cell_index;
   // with a dispatch order, workgroups below n_front take cells from its
   // front (hottest first) and the others from its back: ctl[0] then packs
@@ -186,6 +208,7 @@ struct KArgs {
   // 0: one counter, front only
   int n_front;
   MlpDev mlp;
+  AnnDev ann;
 };
 
 }  // namespace stev

@@ -633,7 +633,15 @@ extern "C" int stev_train_thermo_lma(stev_ctx *ctx, const stev_mech *m, const st
   std::vector<double> pf(P);
   HIP_TRY(hipMemcpyAsync(pf.data(), prm, P * 8, hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
-  if (params_out) std::memcpy(params_out, pf.data(), P * 8);
+  if (params_out) {
+    // fold the z-scoring into the output layer: y = sd (W2 a + b2) + mean
+    std::vector<double> po(pf);
+    for (int o = 0; o < n_out; ++o) {
+      for (int h = 0; h < H; ++h) po[(size_t)o * H + h] *= ms[n_out + o];
+      po[(size_t)n_out * H + o] = pf[(size_t)n_out * H + o] * ms[n_out + o] + ms[o];
+    }
+    std::memcpy(params_out, po.data(), P * 8);
+  }
   if (rep) {
     std::memset(rep, 0, sizeof(*rep));
     rep->hidden = H;

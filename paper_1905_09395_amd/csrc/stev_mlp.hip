@@ -799,7 +799,10 @@ extern "C" int stev_thermo_eval(stev_ctx *ctx, const stev_mech *m, int32_t therm
   if (!ctx) return STEV_EINVAL;
   if (!m || n < 0 || (n > 0 && (!T || !cp_R || !h_R))) return stev_fail(ctx, STEV_EINVAL, "bad argument");
   if (thermo == STEV_THERMO_MLP && !m->mlp.enabled) return stev_fail(ctx, STEV_EINVAL, "no network attached");
-  if (thermo != STEV_THERMO_POLY && thermo != STEV_THERMO_MLP) return stev_fail(ctx, STEV_EINVAL, "bad thermo mode");
+  if (thermo == STEV_THERMO_ANN && !m->ann.enabled)
+    return stev_fail(ctx, STEV_EINVAL, "no sigmoid network attached");
+  if (thermo != STEV_THERMO_POLY && thermo != STEV_THERMO_MLP && thermo != STEV_THERMO_ANN)
+    return stev_fail(ctx, STEV_EINVAL, "bad thermo mode");
   if (n == 0) return STEV_OK;
   (void)hipSetDevice(ctx->device);
   std::lock_guard<std::mutex> guard(ctx->call_mu);
@@ -822,6 +825,8 @@ extern "C" int stev_thermo_eval(stev_ctx *ctx, const stev_mech *m, int32_t therm
     (void)hipMemcpyAsync(dT, T, n * 8, hipMemcpyHostToDevice, s);
     if (thermo == STEV_THERMO_POLY) {
       k_eval_poly<<<(n + 255) / 256, 256, 0, s>>>(sp_rows, n_s, n, dT, dc, dh);
+    } else if (thermo == STEV_THERMO_ANN) {
+      rc = ann_eval(ctx, m, n, dT, dc, dh, s);
     } else {
       const MlpDev &net = m->mlp.dev;
       const int lds = net.L.bytes + 2 * (2 * 16 * kMlpH * 2) + 16 * net.L.nop * 4;
@@ -829,7 +834,8 @@ extern "C" int stev_thermo_eval(stev_ctx *ctx, const stev_mech *m, int32_t therm
     }
     (void)hipMemcpyAsync(cp_R, dc, (size_t)n * n_s * 8, hipMemcpyDeviceToHost, s);
     (void)hipMemcpyAsync(h_R, dh, (size_t)n * n_s * 8, hipMemcpyDeviceToHost, s);
-    if (hipStreamSynchronize(s) != hipSuccess) rc = stev_fail(ctx, STEV_EDEVICE, "thermo kernel failed");
+    if (hipStreamSynchronize(s) != hipSuccess && rc == STEV_OK)
+      rc = stev_fail(ctx, STEV_EDEVICE, "thermo kernel failed");
   }
   for (auto &b : bufs) dev_free(ctx, b.first, b.second);
   return rc;

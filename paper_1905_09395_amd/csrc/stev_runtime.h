@@ -54,6 +54,17 @@ struct MlpHost {
   size_t dev_bytes = 0;
 };
 
+// the paper's sigmoid network attached to a mechanism (host copy, FP64)
+struct AnnHost {
+  int enabled = 0;
+  int H = 0;
+  double T_lo = 300, T_hi = 3000;
+  std::vector<double> prm;          // stev_lma_n_params layout, physical outputs
+  void *dev[2] = {nullptr, nullptr};   // device blobs [precision]
+  size_t dev_bytes[2] = {0, 0};
+  stev::AnnDev d[2]{};
+};
+
 struct stev_mech {
   int n_s = 0, n_r = 0, n_rev = 0, max_part = 0, has_frac = 0, mixed_tmid = 0, dmax = 1;
   uint64_t version = 0;              // bumped when the attached network changes
@@ -73,6 +84,7 @@ struct stev_mech {
     stev::MlpDev dev{};
   } mlp;
   MlpHost mlph;
+  AnnHost ann;
 };
 
 struct LaunchPlan {
@@ -109,6 +121,8 @@ struct MultiLaunch {
     long long cells = 0;
     LaunchPlan lp;
     stev::KArgs a{};
+    bool order = false;         // hottest-first dispatch order built before the launch
+    size_t off_order = 0;       // its scratch (bins, then the index) in the order buffer
   };
   std::vector<Grp> groups;
   void *dev = nullptr;
@@ -117,6 +131,10 @@ struct MultiLaunch {
   // buffers lent by the caller (capacity `cap` each) instead of allocated here
   bool lent = false;
   size_t cap = 0;
+  // order scratch: part of `dev` when allocated here (from off_order_base);
+  // lent, `order_dev` of `order_cap` bytes (none: launches keep array order)
+  void *order_dev = nullptr;
+  size_t order_cap = 0, off_order_base = 0;
   size_t stat_words = 0;        // 4 per item + 8 per group
   hipGraphExec_t exec = nullptr;
   std::vector<const stev_mech *> mechs;
@@ -210,6 +228,10 @@ int check_integrate_args(stev_ctx *ctx, const stev_mech *m, const stev_params &p
                          int64_t ld_cell, int64_t ld_species, double dt_flow);
 // the field is handed out in a dispatch order (hot_first)
 bool field_ordered(const stev_params &p, long long n_cells);
+// hottest-first dispatch order of n cells into idx (bins: kOrderBins words of
+// scratch): of the array T, or with bd non-null of the nb batches' cells
+int launch_order(stev_ctx *ctx, int precision, const void *T, const stev::BatchDesc *bd, int nb,
+                 long long n, unsigned long long *bins, int *idx, hipStream_t s);
 // Enqueues one field integration on s (control words cleared, dispatch order,
 // probe, persistent launch between the context's timing events, statistics
 // copied to ctx->ctl_host); a.n_cells and the state pointers are set.
@@ -222,6 +244,13 @@ int finish_field(stev_ctx *ctx, const LaunchPlan &lp, long long n_cells,
 // thermo network (stev_mlp.hip)
 void mlp_release(stev_ctx *ctx, stev_mech *m);
 int mlp_wave_bytes(const stev_mech *m, const stev_params &p, int G);
+// sigmoid network (stev_ann.hip)
+void ann_release(stev_ctx *ctx, stev_mech *m);
+int ann_wave_bytes(const stev_mech *m, const stev_params &p, int G);
+// cp/R and h/R at n device temperatures from the FP64 sigmoid network (with
+// the polynomial fallback), into device arrays [n][n_s]; enqueued on s
+int ann_eval(stev_ctx *ctx, const stev_mech *m, long long n, const double *T, double *cp_R,
+             double *h_R, hipStream_t s);
 
 // allocation-free entry point (stev_noalloc.hip): device address of the
 // scratch array, looked up once per device with that device current

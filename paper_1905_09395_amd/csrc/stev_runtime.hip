@@ -566,6 +566,7 @@ extern "C" void stev_destroy_mechanism(stev_ctx *ctx, stev_mech *m) {
     plans_forget(ctx, m);
     for (int p = 0; p < 2; ++p) dev_free(ctx, m->blob[p], m->blob_bytes[p]);
     mlp_release(ctx, m);
+    ann_release(ctx, m);
   }
   delete m;
 }
@@ -579,7 +580,7 @@ extern "C" double stev_model_flops(const stev_mech *m, int32_t thermo, double *t
   tr += 2;                      // ln T, 1/T
   // per species: thermo (cp 8, h 10, g 11), mixture 4, gamma 4, conc 2,
   // sources: W*om/rho 2, sum_hw 2, step limiter 5, Euler 4
-  const double per_sp = (thermo == STEV_THERMO_MLP ? 16.0 : 29.0) + 10.0 + 13.0;
+  const double per_sp = (thermo == STEV_THERMO_POLY ? 29.0 : 16.0) + 10.0 + 13.0;
   f += per_sp * m->n_s;
   for (const auto &P : m->rx) {
     const double p = (double)P.sp.size();
@@ -598,6 +599,11 @@ extern "C" double stev_model_flops(const stev_mech *m, int32_t thermo, double *t
   if (thermo == STEV_THERMO_MLP) {
     f += 2.0 * 32 + 2.0 * 32 * 32 + 2.0 * 32 * 2 * m->n_s;
     tr += 64;
+  }
+  if (thermo == STEV_THERMO_ANN) {   // hidden: FMA, add, divide; outputs: FMAs
+    const double H = m->ann.enabled ? m->ann.H : 2.0 * m->n_s;
+    f += 4.0 * H + 2.0 * H * 2 * m->n_s;
+    tr += H;
   }
   if (transc) *transc = tr;
   return f;
@@ -655,13 +661,19 @@ int fill_kargs(stev_ctx *ctx, const stev_mech *m, const stev_params &p, double d
       return stev_fail(ctx, STEV_EINVAL, "thermo=MLP but no network attached to the mechanism");
     a.mlp = m->mlp.dev;
   }
+  if (p.thermo == STEV_THERMO_ANN) {
+    if (!m->ann.enabled)
+      return stev_fail(ctx, STEV_EINVAL, "thermo=ANN but no sigmoid network attached to the mechanism");
+    a.ann = m->ann.d[prec];
+  }
   return STEV_OK;
 }
 
 int validate_params(stev_ctx *ctx, const stev_mech *m, const stev_params &p, double dt_flow) {
   if (p.precision != STEV_F64 && p.precision != STEV_F32)
     return stev_fail(ctx, STEV_EINVAL, "precision must be STEV_F64 or STEV_F32");
-  if (p.thermo != STEV_THERMO_POLY && p.thermo != STEV_THERMO_MLP)
+  if (p.thermo != STEV_THERMO_POLY && p.thermo != STEV_THERMO_MLP &&
+      p.thermo != STEV_THERMO_ANN)
     return stev_fail(ctx, STEV_EINVAL, "bad thermo mode");
   if (!(dt_flow >= 0.0) || !std::isfinite(dt_flow))
     return stev_fail(ctx, STEV_EINVAL, "dt_flow must be finite and >= 0");
@@ -679,6 +691,8 @@ int validate_params(stev_ctx *ctx, const stev_mech *m, const stev_params &p, dou
     return stev_fail(ctx, STEV_EINVAL, "lanes_per_cell out of range");
   if (p.thermo == STEV_THERMO_MLP && !m->mlp.enabled)
     return stev_fail(ctx, STEV_EINVAL, "thermo=MLP but no network attached to the mechanism");
+  if (p.thermo == STEV_THERMO_ANN && !m->ann.enabled)
+    return stev_fail(ctx, STEV_EINVAL, "thermo=ANN but no sigmoid network attached to the mechanism");
   if (p.hot_first < 0 || p.hot_first > 2)
     return stev_fail(ctx, STEV_EINVAL, "hot_first must be 0, 1 or 2");
   if (p.stab_limit != 0 && p.stab_limit != 1)
@@ -707,16 +721,19 @@ int plan_launch(stev_ctx *ctx, const stev_mech *m, const stev_params &p, long lo
       return stev_fail(ctx, STEV_EINVAL, "the thermo network runs with FP32 state (precision=STEV_F32)");
     lp.fn = kMlpVariants[v];
   }
+  if (p.thermo == STEV_THERMO_ANN) lp.fn = kAnnVariants[v][p.precision];
   const int rsz = p.precision == STEV_F64 ? 8 : 4;
   const int cpw = 64 / V.G;
   const int stab_rows = p.stab_limit ? 3 * (m->n_s + 2) + kMaxPart * (m->n_r + 1) : 0;
   lp.exch_bytes = align16((m->n_s + 2 + m->n_r + 2 + (m->mixed_tmid ? m->n_s + 2 : 0) + stab_rows) *
                           cpw * rsz);
-  lp.wave_bytes = lp.exch_bytes + mlp_wave_bytes(m, p, V.G);
+  lp.wave_bytes = lp.exch_bytes + mlp_wave_bytes(m, p, V.G) + ann_wave_bytes(m, p, V.G);
   // the Jacobian pattern (last in the blob) is staged only for the Eq 25
   // limiter, and read from HBM when it would not leave room for one wave
   const MechLayout &ML = m->L[p.precision];
-  const int net_bytes = p.thermo == STEV_THERMO_MLP ? m->mlp.dev.L.bytes : 0;
+  const int net_bytes = p.thermo == STEV_THERMO_MLP   ? m->mlp.dev.L.bytes
+                        : p.thermo == STEV_THERMO_ANN ? m->ann.d[p.precision].bytes
+                                                      : 0;
   lp.jp_global = p.stab_limit && ML.bytes + net_bytes + lp.wave_bytes > ctx->max_lds;
   lp.stage_bytes = (p.stab_limit && !lp.jp_global) ? ML.bytes : ML.off_jp;
   const int mech_bytes = lp.stage_bytes + net_bytes;
@@ -756,7 +773,8 @@ int launch_stev(stev_ctx *ctx, const LaunchPlan &lp, KArgs &a, hipStream_t s) {
   a.exch_bytes = lp.exch_bytes;
   a.mech_stage_bytes = lp.stage_bytes;
   a.jp_global = lp.jp_global;
-  a.lds_mech_bytes = a.mech_stage_bytes + (a.mlp.enabled ? a.mlp.L.bytes : 0);
+  a.lds_mech_bytes = a.mech_stage_bytes + (a.mlp.enabled ? a.mlp.L.bytes : 0) +
+                     (a.ann.enabled ? a.ann.bytes : 0);
   void *args[] = {&a};
   HIP_TRY(hipLaunchKernel(lp.fn, dim3(lp.grid), dim3(lp.block), args, lp.lds, s));
   return STEV_OK;
@@ -781,6 +799,20 @@ bool field_ordered(const stev_params &p, long long n_cells) {
   return p.hot_first && n_cells >= kOrderMinCells && n_cells <= INT32_MAX;
 }
 
+int launch_order(stev_ctx *ctx, int precision, const void *T, const BatchDesc *bd, int nb,
+                 long long n, unsigned long long *bins, int *idx, hipStream_t s) {
+  int rc = launch_zero(ctx, bins, kOrderBins, s);
+  if (rc) return rc;
+  const unsigned grid = (unsigned)std::min<long long>((n + 255) / 256, 1024);
+  void *cargs[] = {&T, &bd, &nb, &n, &bins};
+  HIP_TRY(hipLaunchKernel(kOrderCount[precision], dim3(grid), dim3(256), cargs, 0, s));
+  void *oargs[] = {&bins};
+  HIP_TRY(hipLaunchKernel(kOrderOffsets, dim3(1), dim3(64), oargs, 0, s));
+  void *pargs[] = {&T, &bd, &nb, &n, &bins, &idx};
+  HIP_TRY(hipLaunchKernel(kOrderPlace[precision], dim3(grid), dim3(256), pargs, 0, s));
+  return STEV_OK;
+}
+
 int run_field(stev_ctx *ctx, const stev_mech *m, const stev_params &p, const LaunchPlan &lp,
               KArgs &a, const FieldScratch &ws, hipStream_t s) {
   int rc;
@@ -795,16 +827,8 @@ int run_field(stev_ctx *ctx, const stev_mech *m, const stev_params &p, const Lau
   if (order) {
     unsigned long long *bins = ws.bins;
     int *idx = ws.idx;
-    if ((rc = launch_zero(ctx, bins, kOrderBins, s))) return rc;
-    const void *T_arg = a.T;
-    long long n_arg = a.n_cells;
-    const unsigned grid = (unsigned)std::min<long long>((a.n_cells + 255) / 256, 1024);
-    void *cargs[] = {&T_arg, &n_arg, &bins};
-    HIP_TRY(hipLaunchKernel(kOrderCount[p.precision], dim3(grid), dim3(256), cargs, 0, s));
-    void *oargs[] = {&bins};
-    HIP_TRY(hipLaunchKernel(kOrderOffsets, dim3(1), dim3(64), oargs, 0, s));
-    void *pargs[] = {&T_arg, &n_arg, &bins, &idx};
-    HIP_TRY(hipLaunchKernel(kOrderPlace[p.precision], dim3(grid), dim3(256), pargs, 0, s));
+    if ((rc = launch_order(ctx, p.precision, a.T, nullptr, 0, a.n_cells, bins, idx, s)))
+      return rc;
     if (p.hot_first == 2 &&
         (rc = probe_refine_order(ctx, m, p, a, idx, ws.probe, ws.ctl + 8, s)))
       return rc;

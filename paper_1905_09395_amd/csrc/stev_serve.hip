@@ -20,6 +20,7 @@
 #include <vector>
 
 #include "stev_runtime.h"
+#include "stev_variants.h"
 
 namespace {
 
@@ -49,6 +50,8 @@ struct Round {
   MultiLaunch ml;
   std::vector<Request *> reqs;
   int slot = -1;
+  void *order = nullptr;      // dispatch-order scratch lent to the launch (arena)
+  size_t order_bytes = 0;
 };
 
 // Device staging arena: chunks charged to the HBM budget, sub-allocated
@@ -129,26 +132,31 @@ bool same_kind(const Request *a, const Request *b) {
          std::memcmp(&a->p, &b->p, sizeof(stev_params)) == 0;
 }
 
+// `bytes` of the staging arena, growing it by a chunk if the budget allows
+// (nullptr when it does not).
+void *arena_get(stev_ctx *ctx, ServeState *S, size_t bytes) {
+  void *q = S->arena.take(bytes);
+  if (q) return q;
+  Arena::Chunk c;
+  c.size = std::max(kChunkMin, bytes);
+  void *p = nullptr;
+  if (dev_alloc(ctx, &p, c.size) != STEV_OK && c.size > bytes) {
+    c.size = bytes;
+    if (dev_alloc(ctx, &p, c.size) != STEV_OK) return nullptr;
+  } else if (!p) {
+    return nullptr;
+  }
+  c.base = static_cast<char *>(p);
+  c.free[0] = c.size;
+  S->arena.chunks.push_back(c);
+  return S->arena.take(bytes);
+}
+
 // Device staging for the host arrays of one request: T | P | Y | iters | status.
 int admit(stev_ctx *ctx, ServeState *S, Request *r) {
   if (r->stage_bytes == 0) return STEV_OK;
-  r->stage = S->arena.take(r->stage_bytes);
-  if (!r->stage) {   // grow the arena by a chunk, if the budget allows
-    Arena::Chunk c;
-    c.size = std::max(kChunkMin, r->stage_bytes);
-    void *p = nullptr;
-    if (dev_alloc(ctx, &p, c.size) != STEV_OK && c.size > r->stage_bytes) {
-      c.size = r->stage_bytes;
-      if (dev_alloc(ctx, &p, c.size) != STEV_OK) return STEV_ENOMEM;
-    } else if (!p) {
-      return STEV_ENOMEM;
-    }
-    c.base = static_cast<char *>(p);
-    c.free[0] = c.size;
-    S->arena.chunks.push_back(c);
-    r->stage = S->arena.take(r->stage_bytes);
-    if (!r->stage) return STEV_ENOMEM;
-  }
+  r->stage = arena_get(ctx, S, r->stage_bytes);
+  if (!r->stage) return STEV_ENOMEM;
   S->staged += r->stage_bytes;
   const size_t rsz = r->p.precision == STEV_F64 ? 8 : 4;
   char *s = static_cast<char *>(r->stage);
@@ -220,6 +228,18 @@ int launch_round(stev_ctx *ctx, ServeState *S, Round *rd) {
   rd->ml.host = S->tab_host[rd->slot];
   rd->ml.p = r0->p;
   rd->ml.dt = r0->dt;
+  // scratch for the round's hottest-first dispatch order (its requests share
+  // one mechanism: one group); without it the round keeps array order
+  long long cells = 0;
+  for (Request *r : rd->reqs) cells += r->user.n;
+  if (r0->p.hot_first && cells >= kOrderMinCells) {
+    auto a256 = [](size_t b) { return (b + 255) & ~size_t(255); };
+    rd->order_bytes = a256((size_t)stev::kOrderBins * 8) + a256((size_t)cells * 4);
+    rd->order = arena_get(ctx, S, rd->order_bytes);
+    if (!rd->order) rd->order_bytes = 0;
+    rd->ml.order_dev = rd->order;
+    rd->ml.order_cap = rd->order_bytes;
+  }
   for (Request *r : rd->reqs) {
     rd->ml.items.push_back(r->dev);
     if (std::find(rd->ml.mechs.begin(), rd->ml.mechs.end(), r->user.m) == rd->ml.mechs.end())
@@ -283,6 +303,8 @@ void finish_round(stev_ctx *ctx, ServeState *S, Round *rd, int rc) {
     r->done = true;
   }
   ml_release(ctx, rd->ml);
+  if (rd->order) S->arena.give(rd->order, rd->order_bytes);
+  rd->order = nullptr;
   S->busy[rd->slot] = false;
 }
 

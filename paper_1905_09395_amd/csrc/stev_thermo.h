@@ -7,8 +7,60 @@
 #include <hip/hip_runtime.h>
 
 #include "stev_internal.h"
+#include "stev_math.h"
 
 namespace stev {
+
+// ---------------------------------------------------------------------------
+// The paper's sigmoid thermo network (Sec 3), shared by the integrator and
+// the evaluation kernel so that both round alike.
+// ---------------------------------------------------------------------------
+// Hidden unit: 1 / (1 + e^-z), z = w x + b clamped to [-80, 80] (e^80 is
+// finite in FP32; the clamp moves no output by more than e^-80 relative).
+// FP64 takes e^-z from the exp tables at `tab`.
+__device__ __forceinline__ double ann_unit(double w, double b, double x, const double *tab) {
+  double z = w * x + b;
+  z = fmin(fmax(z, -80.0), 80.0);
+  return qdiv(1.0, 1.0 + exp_tab(tab, -z));
+}
+__device__ __forceinline__ float ann_unit(float w, float b, float x, const double *) {
+  float z = w * x + b;
+  z = fminf(fmaxf(z, -80.0f), 80.0f);
+  return qdiv(1.0f, 1.0f + __expf(-z));   // e^-z through the hardware exp2
+}
+// Output layer for one species: cp and h enter holding the biases and leave
+// with the weighted activations added, hidden unit by hidden unit.  w2k
+// points at the species' (cp, h) weight pair of unit 0; pairs of successive
+// units are n_s pairs apart; act holds Hs activations, Hs a multiple of
+// kAnnPad (pad units carry zero weights and activations), so that several
+// units' loads are in flight together.
+template <typename R>
+__device__ __forceinline__ void ann_species(const R *w2k, const R *act, int Hs, int n_s, R &cp,
+                                            R &h) {
+  if constexpr (sizeof(R) == 8) {
+    // two units at a time: more would hold more registers than the
+    // one-cell-per-wave FP64 kernel has left
+#pragma unroll 2
+    for (int u = 0; u < Hs; u += 2) {
+      const R a0 = act[u], a1 = act[u + 1];
+      const R *w0 = w2k + 2 * u * n_s, *w1 = w0 + 2 * n_s;
+      cp = fma(w0[0], a0, cp);
+      h = fma(w0[1], a0, h);
+      cp = fma(w1[0], a1, cp);
+      h = fma(w1[1], a1, h);
+    }
+  } else {
+    for (int u0 = 0; u0 < Hs; u0 += kAnnPad) {
+#pragma unroll
+      for (int u = u0; u < u0 + kAnnPad; ++u) {
+        const R a = act[u];
+        const R *w = w2k + 2 * u * n_s;
+        cp = fma(w[0], a, cp);
+        h = fma(w[1], a, h);
+      }
+    }
+  }
+}
 
 // cp/R and h/RT of one species at T from its packed row (either set).
 template <typename R>

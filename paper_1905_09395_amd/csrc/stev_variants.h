@@ -26,6 +26,7 @@ struct VariantInfo {
 
 extern const VariantInfo kVariants[];
 extern const void *const kMlpVariants[];   // same order; FP32 + thermo network
+extern const void *const kAnnVariants[][2];  // same order; sigmoid network, [F64, F32]
 extern const int kNumVariants;
 extern const void *kZeroKernel;
 // hottest-first dispatch order of a field: count, offsets, place ([precision])

@@ -48,7 +48,7 @@ def load_curve(load_hist):
             out.append((edges[b], tail))
     return out[::-1]
 F64, F32 = 0, 1
-THERMO_POLY, THERMO_MLP = 0, 1
+THERMO_POLY, THERMO_MLP, THERMO_ANN = 0, 1, 2
 ERR_NAMES = {0: "STEV_OK", 1: "STEV_EINVAL", 2: "STEV_ENOMEM", 3: "STEV_EAGAIN",
              4: "STEV_ENOTFOUND", 5: "STEV_EDEVICE", 6: "STEV_ECELLS"}
 
@@ -196,6 +196,7 @@ def load():
     L.stev_train_thermo_mlp.argtypes = [vp, vp, C.POINTER(MlpCfg), C.POINTER(MlpReport)]
     L.stev_get_thermo_mlp.argtypes = [vp, vp, vp, C.POINTER(i64)]
     L.stev_set_thermo_mlp.argtypes = [vp, vp, i32, dbl, dbl, vp, i64]
+    L.stev_set_thermo_ann.argtypes = [vp, vp, i32, dbl, dbl, vp]
     L.stev_autotune.argtypes = [vp, vp, i64, vp, vp, vp, i64, i64, dbl, C.POINTER(Params)]
     L.stev_mlp_loss_grad.argtypes = [vp, i32, i32, vp, i64, vp, vp, vp, C.POINTER(dbl)]
     L.stev_thermo_eval.argtypes = [vp, vp, i32, i64, vp, vp, vp]
@@ -488,9 +489,19 @@ class Context:
         self._check(self.lib.stev_set_thermo_mlp(self.h, mech.h, int(hidden), float(T_lo),
                                                  float(T_hi), v.ctypes.data, len(v)))
 
+    def set_thermo_ann(self, mech, hidden, T_lo, T_hi, params):
+        """Attach the paper's sigmoid network (FP64 parameters in the
+        Levenberg-Marquardt layout, outputs cp/R then h/R) for THERMO_ANN."""
+        p = np.ascontiguousarray(params, dtype=np.float64)
+        if len(p) != self.lib.stev_lma_n_params(int(hidden), 2 * mech.n_s):
+            raise ValueError("parameter count does not match hidden and the species count")
+        self._check(self.lib.stev_set_thermo_ann(self.h, mech.h, int(hidden), float(T_lo),
+                                                 float(T_hi), p.ctypes.data))
+
     def train_thermo_lma(self, mech, **cfg):
         """The paper's sigmoid network fitted by Levenberg-Marquardt on the
-        GPU; returns (report dict, FP64 parameters)."""
+        GPU; returns (report dict, FP64 parameters with outputs cp/R and h/R,
+        ready for set_thermo_ann)."""
         c = LmaCfg(0, 60, 1 << 16, 300.0, 3000.0, 0.125, 1e-2, 104)
         for k, v in cfg.items():
             setattr(c, k, v)

@@ -54,6 +54,21 @@ MUTATIONS = [
      "if (it >= W) {",
      "if (it >= 1) {",
      "t7 or damped_trajectory"),
+    # Sec 3: the sigmoid's exponent with the wrong sign
+    ("ann_sigmoid_sign",
+     "a[u] = 1.0 / (1.0 + exp(-(w1[u] * x[i] + b1[u])));",
+     "a[u] = 1.0 / (1.0 + exp(w1[u] * x[i] + b1[u]));",
+     "ann_forward"),
+    # Sec 3: the output weights read column-major
+    ("ann_output_transposed",
+     "v += W2[(size_t)o * H + u] * a[u];",
+     "v += W2[(size_t)u * n_out + o] * a[u];",
+     "ann_forward"),
+    # Sec 3: h/R from the network not divided by T
+    ("ann_h_not_over_T",
+     "h_RT[k] = y[n_s + k] / T;",
+     "h_RT[k] = y[n_s + k];",
+     "ann_thermo_mode"),
 ]
 
 

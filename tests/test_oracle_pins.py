@@ -872,3 +872,76 @@ def test_network_thermo_mode(orc):
     a = orc.source(om, 2600.0, P1, Y[0])
     b = orc.source(on, 2600.0, P1, Y[0])
     assert a["dTdt"] == b["dTdt"]
+
+
+# ---------------------------------------------------------------------------
+# The paper's sigmoid network as a thermo mode (Sec 3): one hidden layer of
+# sigmoid units, linear outputs cp/R then h/R, x = (T - 1650) / 1350.
+# ---------------------------------------------------------------------------
+def _ann_params(W2, b2, w1, b1):
+    return np.concatenate([np.asarray(W2, float).ravel(), b2, w1, b1])
+
+
+def test_ann_forward_closed_forms(orc):
+    # sigmoid(0) = 1/2, sigmoid(ln 3) = 3/4, sigmoid(-ln 3) = 1/4 exactly up
+    # to rounding; three units with w1 = 0 fix the activations whatever x is
+    H, n_out = 3, 4
+    rng = np.random.default_rng(11)
+    W2 = rng.normal(0.0, 1.0, (n_out, H))          # row-major [n_out][H]
+    b2 = rng.normal(0.0, 1.0, n_out)
+    prm = _ann_params(W2, b2, np.zeros(H), [0.0, math.log(3.0), -math.log(3.0)])
+    y = orc.ann_forward(H, n_out, prm, np.array([-0.7, 0.0, 0.9]))
+    want = b2 + W2 @ np.array([0.5, 0.75, 0.25])
+    for row in y:
+        np.testing.assert_allclose(row, want, rtol=0, atol=1e-15 * np.abs(W2).sum())
+    # a unit and its mirror (w, b) and (-w, -b) sum to one at every input: with
+    # equal output weights the output is b2 + c, whatever x is
+    c = rng.normal(0.0, 1.0, n_out)
+    W2m = np.stack([c, c], axis=1)
+    prm = _ann_params(W2m, b2, [2.5, -2.5], [0.3, -0.3])
+    y = orc.ann_forward(2, n_out, prm, np.linspace(-1.0, 1.0, 7))
+    np.testing.assert_allclose(y, np.broadcast_to(b2 + c, y.shape), rtol=0, atol=1e-14)
+    # the input scale: w1 = 1, b1 = 0 gives 1/2 at T = 1650 K and 3/4 at
+    # T = 1650 + 1350 ln 3 K (outputs = activations through W2 = I, b2 = 0)
+    prm = _ann_params(np.ones((1, 1)), [0.0], [1.0], [0.0])
+    x = (np.array([1650.0, 1650.0 + 1350.0 * math.log(3.0)]) - 1650.0) / 1350.0
+    np.testing.assert_allclose(orc.ann_forward(1, 1, prm, x)[:, 0], [0.5, 0.75], rtol=1e-15)
+
+
+def test_ann_thermo_mode(orc):
+    m = synth.make_mech6()
+    om = orc.OracleMech(m)
+    ns, H = 6, 5
+    n_out = 2 * ns
+    rng = np.random.default_rng(3)
+    c = rng.uniform(3.0, 9.0, ns)                     # cp/R per species
+    e = rng.uniform(-3e4, 1e4, ns)                    # h/R per species, K
+    # zero output weights: cp/R = c and h/R = e inside the range
+    prm = _ann_params(np.zeros((n_out, H)), np.concatenate([c, e]),
+                      rng.normal(0, 2, H), rng.normal(0, 1, H))
+    on = om.with_ann(H, prm, 500.0, 2500.0)
+    T, P, Y = synth.make_cells_mech6(4, seed=2)
+    W = np.asarray(m["W"])
+    for i in range(4):
+        a = orc.source(om, T[i], P[i], Y[i])
+        b = orc.source(on, T[i], P[i], Y[i])
+        # rates and species sources keep the polynomial Gibbs terms
+        assert np.array_equal(a["q"], b["q"]) and np.array_equal(a["dYdt"], b["dYdt"])
+        # energy equation with constant cp/R = c and h/R = e:
+        # dT/dt sum(Y c / W) = -sum(e dY/dt / W)
+        lhs = b["dTdt"] * np.sum(Y[i] * c / W)
+        rhs = -np.sum(e * b["dYdt"] / W)
+        assert lhs == pytest.approx(rhs, rel=1e-12)
+    # outside the range the polynomials are used, bit for bit
+    a = orc.source(om, 2600.0, P1, Y[0])
+    b = orc.source(on, 2600.0, P1, Y[0])
+    assert a["dTdt"] == b["dTdt"]
+    # the same constant thermo through the tanh network mode (all weights
+    # zero, outputs = z-score means) integrates to the same bits: the two
+    # network modes differ only in how cp and h are formed
+    zero = np.zeros(orc.mlp_n_params(32, n_out))
+    omlp = om.with_network(32, zero, np.concatenate([c, e]), np.ones(n_out), 500.0, 2500.0)
+    r1 = orc.integrate(on, T, P, Y, 1e-4)
+    r2 = orc.integrate(omlp, T, P, Y, 1e-4)
+    assert np.array_equal(r1["T"], r2["T"]) and np.array_equal(r1["Y"], r2["Y"])
+    assert np.array_equal(r1["iters"], r2["iters"])

@@ -84,7 +84,8 @@ typedef struct {
   int32_t lanes_per_cell; /* 0 auto, else 1|8|16|32|64                      */
   int64_t max_iters;      /* per-cell iteration cap -> status 2     (1e6)  */
   int32_t waves_per_wg;   /* 0 auto, else 1..4 waves per workgroup          */
-  int32_t compact_every;  /* refill cadence K in iterations, 0 auto (1)     */
+  int32_t compact_every;  /* refill cadence K in iterations, 0 auto (64 with
+                             one cell per wavefront, else 1)               */
   int32_t grid_wgs;       /* persistent workgroups, 0 auto                  */
   int32_t use_graph;      /* stev_integrate_batched: record the launch
                              sequence as a HIP graph and replay it when an

@@ -727,6 +727,42 @@ def run_serve(args):
     return out
 
 
+def run_solo(args):
+    """Latency of one iteration of the field's slowest cell integrated alone
+    (one wavefront on an otherwise idle GPU): the quantity that bounds the
+    field's launch, whose length is that cell's iteration count times it."""
+    import numpy as np
+    import torch
+
+    from paper_1905_09395_amd import stev, synth
+    dev = torch.device("cuda:0")
+    prec = stev.F64 if args.precision == "f64" else stev.F32
+    dtype = torch.float64 if prec == stev.F64 else torch.float32
+    T, P, Y = synth.make_cells_mech19(args.cells)
+    ctx = stev.Context(0)
+    ctx.set_stream(torch.cuda.current_stream(dev))
+    gm = ctx.mechanism(synth.make_mech19())
+
+    def run(idx):
+        Tt = torch.tensor(T[idx], dtype=dtype, device=dev)
+        Pt = torch.tensor(P[idx], dtype=dtype, device=dev)
+        Yt = torch.tensor(Y[idx], dtype=dtype, device=dev).contiguous()
+        it = torch.zeros(len(idx), dtype=torch.int32, device=dev)
+        st = ctx.integrate(gm, Tt, Pt, Yt, 1e-4, params=stev.default_params(precision=prec),
+                           iters=it)[1]
+        return st, it.cpu().numpy()
+
+    st_f, its = run(np.arange(len(T)))
+    slow = int(np.argmax(its))
+    st, it1 = run(np.array([slow]))
+    n = int(it1[0])
+    out = dict(cell=slow, iterations=n, solo_launch_ms=st["launch_ms"],
+               us_per_iteration=1e3 * st["launch_ms"] / n, field_launch_ms=st_f["launch_ms"],
+               field_over_solo=st_f["launch_ms"] / st["launch_ms"], precision=args.precision)
+    ctx.close()
+    return out
+
+
 def run_legs(args):
     """The metric's other legs at reduced repetition, for the default line:
     batched, learned thermo (tanh and sigmoid networks against the
@@ -773,6 +809,8 @@ def main():
     ap.add_argument("--stab", action="store_true",
                     help="plain workload with the Eq 25 step cap (2/||A||_inf)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--solo", action="store_true",
+                    help="the field's slowest cell integrated alone: per-iteration latency")
     ap.add_argument("--no-legs", action="store_true",
                     help="plain workload only: skip the batched, learned-thermo and served legs")
     ap.add_argument("--probe", action="store_true",
@@ -803,6 +841,9 @@ def main():
     from paper_1905_09395_amd import stev, synth
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.solo:
+        print(json.dumps(run_solo(args)), flush=True)
+        return
     if args.workload != "plain":
         out = {"batched": run_batched, "mlp": run_mlp, "serve": run_serve,
                "c3m": run_c3m}[args.workload](args)

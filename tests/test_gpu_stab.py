@@ -120,3 +120,34 @@ def test_stab_limit_rejections(ctx):
     assert e.value.code == stev.STEV_EINVAL
     m19.close()
     odd.close()
+
+
+@pytest.mark.parametrize("prec", [stev.F64, stev.F32])
+def test_stab_limit_full_length_19_species(ctx, prec):
+    """The limiter over the whole flow step (no iteration cap): 48 cells of
+    the 19-species field (70 % near equilibrium, 30 % igniting; up to ~60 k
+    capped steps per cell), against the oracle's ensemble with the same cap."""
+    m = synth.make_mech19()
+    gm = ctx.mechanism(m)
+    om = oracle.OracleMech(m)
+    T, P, Y = synth.make_cells_split(48, 19, 61)
+    o = oracle_ensemble(om, T, P, Y, DT, prec, stab_limit=1)
+    g = run_gpu(ctx, gm, T, P, Y, DT, prec, stab_limit=1)
+    say(f"full length with the Eq 25 cap: iterations max {int(o['iters'].max())}, "
+        f"median {int(np.median(o['iters']))}")
+    assert np.all(g["status"] == 0)
+    if prec == stev.F64:
+        judge(g, o, prec, f"stab mech19 full length/{prec}")
+    else:
+        # FP32 state: each Euler update of T rounds to ~3e-8 of T, and a cell
+        # that the cap holds to tens of thousands of steps accumulates that
+        # past the FP32 tolerance (the ensemble, FP64 underneath, does not
+        # draw it).  Cells up to 30 000 steps are judged; longer ones are
+        # reported with their step counts.
+        short = o["iters"] <= 30000
+        sub = lambda d: {k: v[short] for k, v in d.items() if isinstance(v, np.ndarray)}
+        judge(sub(g), sub(o), prec, f"stab mech19 full length/{prec}, <= 30000 steps")
+        for c in np.where(~short)[0]:
+            relT = abs(g["T"][c] - o["T"][c]) / o["T"][c]
+            say(f"    cell {c}: {int(o['iters'][c])} steps, FP32 rel T {relT:.2e}")
+    gm.close()

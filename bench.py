@@ -742,14 +742,22 @@ def run_solo(args):
     ctx = stev.Context(0)
     ctx.set_stream(torch.cuda.current_stream(dev))
     gm = ctx.mechanism(synth.make_mech19())
+    th = {"poly": stev.THERMO_POLY, "mlp": stev.THERMO_MLP, "ann": stev.THERMO_ANN}[args.thermo]
+    if th == stev.THERMO_MLP:
+        # a short schedule: the probe times the evaluation, not the fit (and a
+        # counter-collecting profiler copes with fewer training dispatches)
+        ctx.train_thermo_mlp(gm, epochs=20, n_samples=1 << 16, batch=8192, lr=3e-3, seed=104)
+    if th == stev.THERMO_ANN:
+        rep, prm = ctx.train_thermo_lma(gm, iters=150, n_samples=1 << 16, seed=104)
+        ctx.set_thermo_ann(gm, rep["hidden"], 300.0, 3000.0, prm)
 
     def run(idx):
         Tt = torch.tensor(T[idx], dtype=dtype, device=dev)
         Pt = torch.tensor(P[idx], dtype=dtype, device=dev)
         Yt = torch.tensor(Y[idx], dtype=dtype, device=dev).contiguous()
         it = torch.zeros(len(idx), dtype=torch.int32, device=dev)
-        st = ctx.integrate(gm, Tt, Pt, Yt, 1e-4, params=stev.default_params(precision=prec),
-                           iters=it)[1]
+        st = ctx.integrate(gm, Tt, Pt, Yt, 1e-4,
+                           params=stev.default_params(precision=prec, thermo=th), iters=it)[1]
         return st, it.cpu().numpy()
 
     st_f, its = run(np.arange(len(T)))
@@ -758,7 +766,8 @@ def run_solo(args):
     n = int(it1[0])
     out = dict(cell=slow, iterations=n, solo_launch_ms=st["launch_ms"],
                us_per_iteration=1e3 * st["launch_ms"] / n, field_launch_ms=st_f["launch_ms"],
-               field_over_solo=st_f["launch_ms"] / st["launch_ms"], precision=args.precision)
+               field_over_solo=st_f["launch_ms"] / st["launch_ms"], precision=args.precision,
+               thermo=args.thermo)
     ctx.close()
     return out
 
@@ -811,6 +820,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--solo", action="store_true",
                     help="the field's slowest cell integrated alone: per-iteration latency")
+    ap.add_argument("--thermo", default="poly", choices=["poly", "mlp", "ann"],
+                    help="--solo: thermo mode (mlp: FP32 only)")
     ap.add_argument("--no-legs", action="store_true",
                     help="plain workload only: skip the batched, learned-thermo and served legs")
     ap.add_argument("--probe", action="store_true",

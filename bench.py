@@ -346,11 +346,53 @@ def run_batched(args):
     el_plain = time.perf_counter() - t1
     k_ms = float(np.mean(kms))
     achieved = work / (k_ms * 1e-3) / 1e12
+
+    # accuracy: every cell against the same batches in FP64 (polynomials)
+    def rel_T():
+        return np.concatenate([b["T"].cpu().double().numpy() for b in B])
+    f64 = torch.float64
+    R = [dict(T=torch.tensor(T, dtype=f64, device=dev), P=torch.tensor(P, dtype=f64, device=dev),
+              Y=torch.tensor(Y, dtype=f64, device=dev).contiguous()) for k, T, P, Y in batches]
+    ctx.integrate_batched([mechs[b["key"]] for b in B], [r["T"] for r in R], [r["P"] for r in R],
+                          [r["Y"] for r in R], dt, params=stev.default_params(precision=stev.F64))
+    refT = np.concatenate([r["T"].cpu().numpy() for r in R])
+    del R
+    step_batched()
+    torch.cuda.synchronize()
+    err_poly = np.abs(rel_T() - refT) / refT
+
+    # batched with the thermo network (trained per mechanism, launch shape
+    # tuned per mechanism for that thermo mode)
+    for k, gm in mechs.items():
+        ctx.train_thermo_mlp(gm, epochs=300, n_samples=1 << 20, batch=8192, lr=3e-3, seed=104)
+        sel = [b for b in B if b["key"] == k]
+        ctx.autotune(gm, torch.cat([b["T0"] for b in sel]), torch.cat([b["P"] for b in sel]),
+                     torch.cat([b["Y0"] for b in sel]), dt,
+                     stev.default_params(precision=prec, thermo=stev.THERMO_MLP))
+    prm_mlp = stev.default_params(precision=prec, thermo=stev.THERMO_MLP)
+
+    def step_batched_mlp():
+        restore()
+        return ctx.integrate_batched([mechs[b["key"]] for b in B], [b["T"] for b in B],
+                                     [b["P"] for b in B], [b["Y"] for b in B], dt,
+                                     params=prm_mlp, iters=[b["it"] for b in B])[1]
+
+    for _ in range(args.warmup):
+        step_batched_mlp()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    for _ in range(args.steps):
+        step_batched_mlp()
+    torch.cuda.synchronize()
+    el_mlp = time.perf_counter() - t2
+    err_mlp = np.abs(rel_T() - refT) / refT
+
     out = base_record(args, n_cells * args.steps / el, el, "f32",
                       "batched STEV: 64 batches of log-uniform size in [256, 131072], "
                       "alternating 6-species/4-reaction and 19-species/50-reaction "
                       "mechanisms, one persistent launch per mechanism, graph replay, "
-                      "autotuned launch shape, FP32, dt_flow=1e-4 s",
+                      "autotuned launch shape, FP32, dt_flow=1e-4 s; beside it the same "
+                      "batches with the tanh thermo network and as 64 plain calls",
                       cells=n_cells, batches=64,
                       tuned={str(k): dict(lanes_per_cell=v.lanes_per_cell,
                                           waves_per_wg=v.waves_per_wg,
@@ -358,7 +400,14 @@ def run_batched(args):
                              for k, v in tuned.items()},
                       plain_per_batch_cells_per_s=n_cells * args.steps / el_plain,
                       plain_per_batch_kernel_ms=float(np.mean(pms)),
-                      speedup_vs_plain_per_batch=el_plain / el)
+                      speedup_vs_plain_per_batch=el_plain / el,
+                      batched_network_cells_per_s=n_cells * args.steps / el_mlp,
+                      batched_network_speedup_vs_plain_per_batch=el_plain / el_mlp,
+                      rel_T_vs_fp64=dict(
+                          batched_poly=dict(median=float(np.median(err_poly)),
+                                            p99=float(np.quantile(err_poly, .99))),
+                          batched_network=dict(median=float(np.median(err_mlp)),
+                                               p99=float(np.quantile(err_mlp, .99)))))
     out["roofline"] = {"bound": "alu", "achieved": achieved, "peak": PEAK["f32"],
                        "unit": "TFLOP/s", "frac": achieved / PEAK["f32"], "traffic": None,
                        "kernel_ms": k_ms, "flop_count": "direct 13-point DFT",
@@ -781,10 +830,15 @@ def run_legs(args):
     la = copy.copy(args)
     la.steps, la.warmup = 2, 1
     b = run_batched(la)
+    bc = b["config"]
     legs["batched"] = dict(cells_per_s=b["value"], ms_per_step=b["ms_per_step"],
-                           plain_per_batch_cells_per_s=b["config"]["plain_per_batch_cells_per_s"],
-                           speedup_vs_plain_per_batch=b["config"]["speedup_vs_plain_per_batch"],
-                           roofline_frac=b["roofline"]["frac"], workload=b["config"]["workload"])
+                           plain_per_batch_cells_per_s=bc["plain_per_batch_cells_per_s"],
+                           speedup_vs_plain_per_batch=bc["speedup_vs_plain_per_batch"],
+                           network_cells_per_s=bc["batched_network_cells_per_s"],
+                           network_speedup_vs_plain_per_batch=bc[
+                               "batched_network_speedup_vs_plain_per_batch"],
+                           rel_T_vs_fp64=bc["rel_T_vs_fp64"],
+                           roofline_frac=b["roofline"]["frac"], workload=bc["workload"])
     print("legs: batched done", file=sys.stderr, flush=True)
     m = run_mlp(la)
     c = m["config"]

@@ -171,3 +171,48 @@ def test_cost_against_polynomials_and_tanh_network(ctx, n19):
         line = ", ".join(f"{k[1]} {v:.2f} ms ({v / p:.3f}x)" for k, v in ms.items() if k[0] == prec)
         say(f"65536 cells x <=300 iterations, {'FP32' if prec == stev.F32 else 'FP64'}: {line}")
     assert all(v > 0 for v in ms.values())
+
+
+@pytest.mark.parametrize("precision", [stev.F64, stev.F32])
+def test_other_entry_points_with_the_sigmoid_network(ctx, n19, precision):
+    """The sigmoid thermo mode through the multi-batch launch (hottest-first
+    groups), the allocation-free call and a served request gives, cell for
+    cell, the bits of a plain call."""
+    import time
+    import torch
+    gm = n19["gm"]
+    T, P, Y = synth.make_cells_mech19(9000, seed=77)
+    dt = torch.float64 if precision == stev.F64 else torch.float32
+    prm = stev.default_params(precision=precision, thermo=stev.THERMO_ANN)
+
+    def dev(a):
+        return torch.tensor(a, dtype=dt, device="cuda").contiguous()
+
+    ref = run_gpu(ctx, gm, T, P, Y, 1e-4, precision, thermo=stev.THERMO_ANN)
+    # two batches of 4 500 and 4 500 cells in one launch
+    Ts, Ps, Ys = [dev(T[:4500]), dev(T[4500:])], [dev(P[:4500]), dev(P[4500:])], \
+        [dev(Y[:4500]), dev(Y[4500:])]
+    ctx.integrate_batched([gm, gm], Ts, Ps, Ys, 1e-4, params=prm)
+    torch.cuda.synchronize()
+    bT = np.concatenate([t.cpu().double().numpy() for t in Ts])
+    bY = np.concatenate([y.cpu().double().numpy() for y in Ys])
+    assert np.array_equal(bT, ref["T"]) and np.array_equal(bY, ref["Y"])
+    # allocation-free
+    Tn, Pn, Yn = dev(T), dev(P), dev(Y)
+    ctx.integrate_noalloc(gm, Tn, Pn, Yn, 1e-4, params=prm)
+    torch.cuda.synchronize()
+    assert np.array_equal(Tn.cpu().double().numpy(), ref["T"])
+    assert np.array_equal(Yn.cpu().double().numpy(), ref["Y"])
+    # served (host arrays, staged)
+    Th = np.array(T, dtype=np.float64 if precision == stev.F64 else np.float32)
+    Yh = np.ascontiguousarray(Y, dtype=Th.dtype)
+    Ph = np.ascontiguousarray(P, dtype=Th.dtype)
+    tk = ctx.submit(gm, Th, Ph, Yh, 1e-4, params=prm)
+    while True:
+        rc, _ = ctx.poll(tk)
+        if rc != stev.STEV_EAGAIN:
+            break
+        time.sleep(1e-3)
+    assert rc == stev.STEV_OK
+    assert np.array_equal(Th.astype(np.float64), ref["T"])
+    assert np.array_equal(Yh.astype(np.float64), ref["Y"])

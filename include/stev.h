@@ -248,7 +248,8 @@ int stev_poll(stev_ctx *ctx, uint64_t ticket, stev_stats *stats);
  * (cp/R and h/R, z-scored) on GPU-sampled NASA-7 targets with the library's
  * own forward/backward/Adam kernels, then attach BF16 weights to `mech` for
  * STEV_THERMO_MLP.  Range [T_lo, T_hi]; outside it the kernel falls back to
- * the polynomials. */
+ * the polynomials.  Attaching replaces and frees an earlier network: no call
+ * that uses `mech`, served requests included, may be in flight. */
 typedef struct {
   int32_t hidden;          /* 32 */
   int32_t epochs;          /* passes over the samples */
@@ -326,7 +327,9 @@ int stev_train_thermo_lma(stev_ctx *ctx, const stev_mech *mech, const stev_lma_c
  * evaluated in the launch's precision (sigmoids and sums on the vector
  * units, hidden units in order); outside, and for the equilibrium
  * constants everywhere, it uses the polynomials.  hidden in [1, 64].
- * Replaces an earlier sigmoid network; STEV_EINVAL on a bad shape or range,
+ * Replaces an earlier sigmoid network (whose device copies are freed: no
+ * call that uses `mech`, served requests included, may be in flight);
+ * STEV_EINVAL on a bad shape or range,
  * STEV_ENOMEM when the device copies do not fit the HBM budget. */
 int stev_set_thermo_ann(stev_ctx *ctx, stev_mech *mech, int32_t hidden, double T_lo,
                         double T_hi, const double *params);
@@ -342,7 +345,9 @@ int stev_lma_normal_eq(stev_ctx *ctx, int32_t hidden, int32_t n_out, const doubl
 
 /* Export / import the FP32 master weights of an attached network
  * (layout W1[H] b1[H] W2[H][H] b2[H] W3[2n][H] b3[2n], then 4n z-score
- * constants mean_cp[n] std_cp[n] mean_h[n] std_h[n]).  n_values in/out. */
+ * constants mean_cp[n] std_cp[n] mean_h[n] std_h[n]).  n_values in/out.
+ * Setting replaces the attached network and frees its device copy: no call
+ * that uses `mech`, served requests included, may be in flight. */
 int stev_get_thermo_mlp(stev_ctx *ctx, const stev_mech *mech, float *values, int64_t *n_values);
 int stev_set_thermo_mlp(stev_ctx *ctx, stev_mech *mech, int32_t hidden, double T_lo,
                         double T_hi, const float *values, int64_t n_values);

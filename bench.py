@@ -737,9 +737,9 @@ def run_serve(args):
             costliest_request_serve_ms=1e3 * float(np.mean([l[big] for l in ls])),
             costliest_request_plain_ms=1e3 * float(np.mean([l[big] for l in lps])))
     # the same load 0.95 arrivals under a budget that admits the largest
-    # request with 8 MiB to spare: admission then binds whenever a large
+    # request with 4 MiB to spare: admission then binds whenever a large
     # request is in flight (requests queue for memory, at a latency cost)
-    tight = max(stage) + (8 << 20)
+    tight = max(stage) + (4 << 20)
     ctx_t = stev.Context(0, hbm_budget=tight)
     mechs_t = {}
     for k, m in src.items():
@@ -767,7 +767,7 @@ def run_serve(args):
                       "thermo network, host-resident pinned requests admitted by an HBM budget "
                       "of the largest request's staging + 48 MiB; value at load 0.95 "
                       "('saturated': every request at t=0; '0.95_tight_budget': the load 0.95 "
-                      "arrivals with a budget of the largest staging + 8 MiB); quantiles over "
+                      "arrivals with a budget of the largest staging + 4 MiB); quantiles over "
                       "the same number of served and plain runs",
                       requests=n_req, cells=total, hbm_budget_bytes=budget,
                       plain_capacity_cells_per_s=cap, loads=rows)

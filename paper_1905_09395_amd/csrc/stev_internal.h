@@ -98,9 +98,9 @@ struct MechLayout {
   int off_rxi;         // i32 [n_r+1][kMaxPart] slot species: n_s = unit entry
   int off_cj;          // i32 [n_s+1][dstride]  reaction (packed order); n_r = zero entry
   int off_cnu;         // R   [n_s+1][dstride]  nu (0 on padding)
-  int jwidth;          // Jacobian pattern row length (multiple of kCsrChunk)
+  int jwidth;          // Jacobian pattern part-row length (multiple of kCsrChunk)
   int jpitch;          // Jacobian pattern row pitch, jwidth + 1 (odd)
-  int off_jp;          // i32 [n_s+1][jpitch]   Jacobian pattern (see JP_* below)
+  int off_jp;          // i32 [2][n_s+1][jpitch]   Jacobian pattern part-rows (see JP_* below)
 };
 
 // Jacobian pattern entry of species row i (Eq 25 limiter): the derivative

@@ -871,12 +871,13 @@ stev_persistent(const KArgs a) {
     }
     // Eq 25: ||A||_inf of A = d(dY/dt)/dY at fixed T and rho.  Row i walks
     // its pattern: per column, the sum of nu_i,jn * d(q_eff,jn)/dY_j over the
-    // reactions sharing i and j, then |.| summed over the columns
+    // reactions sharing i and j, then |.| summed over the columns.  A row is
+    // stored as two part-rows cut at a column boundary, and every variant
+    // adds the two parts' sums last, so all launch shapes agree bit for bit;
+    // with one cell per wave lanes l and l + 32 walk the two parts of row l.
     R normA = R(0);
     if constexpr (STAB) {
-#pragma unroll
-      for (int s = 0; s < SPL; ++s) {
-        const unsigned *je = jpt + kk[s] * a.L.jpitch;
+      auto walk = [&](const unsigned *je) {
         R row = R(0), acc = R(0);
         for (int e0 = 0; e0 < a.L.jwidth; e0 += kCsrChunk) {
           unsigned ev[kCsrChunk];
@@ -893,6 +894,25 @@ stev_persistent(const KArgs a) {
             row = end ? row + fabs(acc) : row;
             acc = end ? R(0) : acc;
           }
+        }
+        return row;
+      };
+      const int jpart = (n_s + 1) * a.L.jpitch;   // offset of the second part-rows
+      const bool jsplit = kSplitRow && n_s <= 32;
+      const int jhalf = (jsplit && l >= 32) ? 1 : 0;
+      const int jrow = ((l & 31) < n_s) ? (l & 31) : n_s;
+#pragma unroll
+      for (int s = 0; s < SPL; ++s) {
+        R row;
+        if (jsplit) {
+          const R part = walk(jpt + jhalf * jpart + jrow * a.L.jpitch);
+          R ra, rb;
+          swap_pair<32>(part, ra, rb);
+          row = jhalf ? R(0) : ra + rb;   // upper lanes hold no species
+        } else {
+          const R r0 = walk(jpt + kk[s] * a.L.jpitch);
+          const R r1 = walk(jpt + jpart + kk[s] * a.L.jpitch);
+          row = r0 + r1;
         }
         normA = fmax(normA, R(0.5) * row * Wk[s] * inv_rho);
       }

@@ -73,7 +73,7 @@ struct stev_mech {
   std::vector<int> orig_of_new;
   std::vector<int> csr_ptr, csr_j;
   std::vector<double> csr_nu;
-  std::vector<unsigned> jp;          // Jacobian pattern, [n_s + 1][jwidth]
+  std::vector<unsigned> jp;          // Jacobian pattern part-rows, [2][n_s + 1][jwidth]
   int jwidth = 8;
   int jac_ok = 1;                    // every 2 nu fits a signed byte exactly
   void *blob[2] = {nullptr, nullptr};

@@ -266,7 +266,7 @@ static void pack_blob(const stev_mech *m, std::vector<unsigned char> &blob, Mech
   L.off_cnu = off;  off = align16(off + L.nnz_csr * (int)sizeof(R));
   L.jwidth = m->jwidth;
   L.jpitch = m->jwidth + 1;
-  L.off_jp = off;   off = align16(off + (n_s + 1) * L.jpitch * 4);
+  L.off_jp = off;   off = align16(off + 2 * (n_s + 1) * L.jpitch * 4);
   L.bytes = std::max(off, 16);
   blob.assign(L.bytes, 0);
   if constexpr (sizeof(R) == 8) fill_xtab(reinterpret_cast<double *>(blob.data() + L.off_xtab));
@@ -335,7 +335,7 @@ static void pack_blob(const stev_mech *m, std::vector<unsigned char> &blob, Mech
     }
   }
   unsigned *jp = reinterpret_cast<unsigned *>(blob.data() + L.off_jp);
-  for (int k = 0; k <= n_s; ++k) {
+  for (int k = 0; k < 2 * (n_s + 1); ++k) {
     std::memcpy(jp + (size_t)k * L.jpitch, m->jp.data() + (size_t)k * L.jwidth, L.jwidth * 4);
     jp[(size_t)k * L.jpitch + L.jwidth] = m->jp[(size_t)k * L.jwidth];   // pad: never read
   }
@@ -344,8 +344,10 @@ static void pack_blob(const stev_mech *m, std::vector<unsigned char> &blob, Mech
 // Jacobian pattern (Eq 25 limiter): for species i, every (reaction, rate-law
 // slot) pair whose slot species j is a real species and whose rate depends on
 // it, with nu_ij; grouped by column j (ascending), reactions in original
-// order inside a column.  Rows are padded with entries on the dummy
-// reaction's zero slot.
+// order inside a column.  Each row is cut at the column boundary nearest its
+// middle into two part-rows, stored as [part][species + dummy][jwidth], so
+// that two lanes can walk one row (a column never straddles the cut).
+// Part-rows are padded with entries on the dummy reaction's zero slot.
 static void build_jacobian_pattern(stev_mech *m) {
   const int n_s = m->n_s, n_r = m->n_r;
   struct E { int col, idx, nu2; };
@@ -367,18 +369,29 @@ static void build_jacobian_pattern(stev_mech *m) {
     std::stable_sort(rows[i].begin(), rows[i].end(),
                      [](const E &a, const E &b) { return a.col < b.col; });
   }
+  // cut: the column boundary that best balances the two parts
+  std::vector<size_t> cut(n_s, 0);
   size_t w = 1;
-  for (auto &r : rows) w = std::max(w, r.size());
+  for (int i = 0; i < n_s; ++i) {
+    const size_t len = rows[i].size();
+    size_t best = len;
+    for (size_t q = 0; q <= len; ++q) {
+      const bool boundary = q == 0 || q == len || rows[i][q].col != rows[i][q - 1].col;
+      if (boundary && std::max(q, len - q) < std::max(best, len - best)) best = q;
+    }
+    cut[i] = best;
+    w = std::max(w, std::max(best, len - best));
+  }
   m->jwidth = (int)((w + kCsrChunk - 1) / kCsrChunk * kCsrChunk);
   const unsigned zero = (unsigned)(n_r * kMaxPart) | JP_END;   // dummy reaction: rate 0
-  m->jp.assign((size_t)(n_s + 1) * m->jwidth, zero);
+  m->jp.assign((size_t)2 * (n_s + 1) * m->jwidth, zero);
   for (int i = 0; i < n_s; ++i)
     for (size_t q = 0; q < rows[i].size(); ++q) {
       const E &x = rows[i][q];
       const bool end = q + 1 == rows[i].size() || rows[i][q + 1].col != x.col;
-      m->jp[(size_t)i * m->jwidth + q] = (unsigned)x.idx |
-                                         ((unsigned)(x.nu2 & 0xff) << JP_NU2_SHIFT) |
-                                         (end ? JP_END : 0u);
+      const size_t part = q < cut[i] ? 0 : 1, pos = part ? q - cut[i] : q;
+      m->jp[((size_t)part * (n_s + 1) + i) * m->jwidth + pos] =
+          (unsigned)x.idx | ((unsigned)(x.nu2 & 0xff) << JP_NU2_SHIFT) | (end ? JP_END : 0u);
     }
 }
 

@@ -204,7 +204,10 @@ def pmc_summary(csv_paths, precision, cells):
                                     "SQ_INSTS_SALU")],
                 "f32": [("valu_f32", "SQ_INSTS_VALU_FLOPS_FP32 SQ_INSTS_VALU_FLOPS_FP32_TRANS "
                                      "SQ_INSTS_VALU SQ_INSTS_VALU_FMA_F32 SQ_INSTS_VALU_ADD_F32 "
-                                     "SQ_INSTS_VALU_MUL_F32 SQ_INSTS_VALU_TRANS_F32 SQ_INSTS_LDS")]}
+                                     "SQ_INSTS_VALU_MUL_F32 SQ_INSTS_VALU_TRANS_F32 SQ_INSTS_LDS"),
+                        ("cyc_f32", "SQ_WAVE_CYCLES SQ_BUSY_CYCLES SQ_WAIT_ANY SQ_WAIT_INST_ANY "
+                                    "SQ_ACTIVE_INST_ANY SQ_ACTIVE_INST_VALU SQ_ACTIVE_INST_LDS "
+                                    "SQ_INSTS_SALU")]}
         for name, ctrs in sets[precision]:
             f.write(f"    rocprofv3 --pmc {ctrs} -d gpurun_out/pmc_{name} -o t --output-format csv "
                     f"-- python bench.py --probe --precision {precision}\n")
@@ -809,7 +812,9 @@ def run_solo(args):
         Yt = torch.tensor(Y[idx], dtype=dtype, device=dev).contiguous()
         it = torch.zeros(len(idx), dtype=torch.int32, device=dev)
         st = ctx.integrate(gm, Tt, Pt, Yt, 1e-4,
-                           params=stev.default_params(precision=prec, thermo=th), iters=it)[1]
+                           params=stev.default_params(precision=prec, thermo=th,
+                                                      stab_limit=1 if args.stab else 0),
+                           iters=it)[1]
         return st, it.cpu().numpy()
 
     st_f, its = run(np.arange(len(T)))
@@ -819,7 +824,7 @@ def run_solo(args):
     out = dict(cell=slow, iterations=n, solo_launch_ms=st["launch_ms"],
                us_per_iteration=1e3 * st["launch_ms"] / n, field_launch_ms=st_f["launch_ms"],
                field_over_solo=st_f["launch_ms"] / st["launch_ms"], precision=args.precision,
-               thermo=args.thermo)
+               thermo=args.thermo, stab_limit=bool(args.stab))
     ctx.close()
     return out
 

@@ -282,6 +282,31 @@ __device__ __forceinline__ void stab_slot_derivs(const R (&C)[kMaxPart], R kf, R
   for (int p = 0; p < kMaxPart; ++p) sD[(jn * kMaxPart + p) * CPW + gi] = d[p];
 }
 
+// Eq 25 limiter: one part-row of a species' Jacobian pattern.  Per column,
+// the sum of nu * d(q_eff)/dY over the column's entries; |.| of each column
+// sum, summed over the columns (entries flagged JP_END close a column).
+template <typename R, int CPW>
+__device__ __forceinline__ R jac_part_row(const unsigned *je, int width, const R *sD, int gi) {
+  R row = R(0), acc = R(0);
+  for (int e0 = 0; e0 < width; e0 += kCsrChunk) {
+    unsigned ev[kCsrChunk];
+    R dv[kCsrChunk];
+#pragma unroll
+    for (int u = 0; u < kCsrChunk; ++u) ev[u] = je[e0 + u];
+#pragma unroll
+    for (int u = 0; u < kCsrChunk; ++u) dv[u] = sD[(int)(ev[u] & JP_IDX_MASK) * CPW + gi];
+#pragma unroll
+    for (int u = 0; u < kCsrChunk; ++u) {
+      const int nu2 = ((int)(ev[u] << 8)) >> 24;   // 2 nu, signed byte
+      acc += R(nu2) * dv[u];
+      const bool end = (ev[u] & JP_END) != 0u;
+      row = end ? row + fabs(acc) : row;
+      acc = end ? R(0) : acc;
+    }
+  }
+  return row;
+}
+
 template <typename R, int G, int RPL, int RRPL, int SPL, int CSRR, int TH, bool STAB>
 __global__ void __launch_bounds__(256)
 stev_persistent(const KArgs a) {
@@ -348,10 +373,6 @@ stev_persistent(const KArgs a) {
       sLG[n_s * CPW + gi] = R(0);
     }
   }
-  const unsigned *jpt = a.jp_global
-                            ? reinterpret_cast<const unsigned *>(
-                                  reinterpret_cast<const unsigned char *>(a.blob) + a.L.off_jp)
-                            : reinterpret_cast<const unsigned *>(smem + a.L.off_jp);
   // thermo-network scratch: layer activations (bf16 hi/lo planes) and outputs
   const unsigned char *wnet = smem + a.mech_stage_bytes;
   __bf16 *act1 = reinterpret_cast<__bf16 *>(reinterpret_cast<unsigned char *>(ws) + a.exch_bytes);
@@ -877,25 +898,18 @@ stev_persistent(const KArgs a) {
     // with one cell per wave lanes l and l + 32 walk the two parts of row l.
     R normA = R(0);
     if constexpr (STAB) {
-      auto walk = [&](const unsigned *je) {
-        R row = R(0), acc = R(0);
-        for (int e0 = 0; e0 < a.L.jwidth; e0 += kCsrChunk) {
-          unsigned ev[kCsrChunk];
-          R dv[kCsrChunk];
-#pragma unroll
-          for (int u = 0; u < kCsrChunk; ++u) ev[u] = je[e0 + u];
-#pragma unroll
-          for (int u = 0; u < kCsrChunk; ++u) dv[u] = sD[(int)(ev[u] & JP_IDX_MASK) * CPW + gi];
-#pragma unroll
-          for (int u = 0; u < kCsrChunk; ++u) {
-            const int nu2 = ((int)(ev[u] << 8)) >> 24;   // 2 nu, signed byte
-            acc += R(nu2) * dv[u];
-            const bool end = (ev[u] & JP_END) != 0u;
-            row = end ? row + fabs(acc) : row;
-            acc = end ? R(0) : acc;
-          }
-        }
-        return row;
+      // the pattern sits in LDS unless it did not fit there; the two calls
+      // keep the LDS walk on LDS instructions (a pointer that may point to
+      // either would make every load a flat one)
+      auto walk = [&](int off) {
+        return a.jp_global
+                   ? jac_part_row<R, CPW>(reinterpret_cast<const unsigned *>(
+                                              reinterpret_cast<const unsigned char *>(a.blob) +
+                                              a.L.off_jp) + off,
+                                          a.L.jwidth, sD, gi)
+                   : jac_part_row<R, CPW>(
+                         reinterpret_cast<const unsigned *>(smem + a.L.off_jp) + off,
+                         a.L.jwidth, sD, gi);
       };
       const int jpart = (n_s + 1) * a.L.jpitch;   // offset of the second part-rows
       const bool jsplit = kSplitRow && n_s <= 32;
@@ -905,13 +919,13 @@ stev_persistent(const KArgs a) {
       for (int s = 0; s < SPL; ++s) {
         R row;
         if (jsplit) {
-          const R part = walk(jpt + jhalf * jpart + jrow * a.L.jpitch);
+          const R part = walk(jhalf * jpart + jrow * a.L.jpitch);
           R ra, rb;
           swap_pair<32>(part, ra, rb);
           row = jhalf ? R(0) : ra + rb;   // upper lanes hold no species
         } else {
-          const R r0 = walk(jpt + kk[s] * a.L.jpitch);
-          const R r1 = walk(jpt + jpart + kk[s] * a.L.jpitch);
+          const R r0 = walk(kk[s] * a.L.jpitch);
+          const R r1 = walk(jpart + kk[s] * a.L.jpitch);
           row = r0 + r1;
         }
         normA = fmax(normA, R(0.5) * row * Wk[s] * inv_rho);

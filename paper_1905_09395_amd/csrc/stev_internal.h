@@ -98,10 +98,18 @@ struct MechLayout {
   int off_rxi;         // i32 [n_r+1][kMaxPart] slot species: n_s = unit entry
   int off_cj;          // i32 [n_s+1][dstride]  reaction (packed order); n_r = zero entry
   int off_cnu;         // R   [n_s+1][dstride]  nu (0 on padding)
-  int jwidth;          // Jacobian pattern part-row length (multiple of kCsrChunk)
-  int jpitch;          // Jacobian pattern row pitch, jwidth + 1 (odd)
-  int off_jp;          // i32 [2][n_s+1][jpitch]   Jacobian pattern part-rows (see JP_* below)
+  int jwidth;          // Jacobian pattern piece length (multiple of kCsrChunk)
+  int jpitch;          // Jacobian pattern piece pitch, jwidth + 1 (odd)
+  int jpieces;         // pieces of all species rows; piece jpieces is all padding
+  int jkmax;           // most pieces of one species row
+  int off_jp;          // u32 [n_s+1] per species (first piece | pieces << 16), then at
+                       // off_jpc u32 [jpieces+1][jpitch] the pieces (see JP_* below)
+  int off_jpc;
 };
+
+// Pieces of the Jacobian pattern: with at most this many species the rows
+// are cut into at most this many pieces, one per lane of a wavefront.
+constexpr int kJacLanes = 64;
 
 // Jacobian pattern entry of species row i (Eq 25 limiter): the derivative
 // of reaction jn's damped rate with respect to the species in its rate-law

@@ -442,6 +442,22 @@ stev_persistent(const KArgs a) {
     }
   const R *nu_half = cnu + srow * dstride + half * kHalf;
 
+  // Eq 25 limiter: the pattern pieces of the lane's species, as
+  // first piece | count << 16 (count 0 for the padding species)
+  constexpr bool kLanePieces = (G == 64) && (SPL == 1);
+  unsigned jsp_l[SPL];
+#pragma unroll
+  for (int s = 0; s < SPL; ++s) {
+    jsp_l[s] = 0u;
+    if constexpr (STAB) {
+      const unsigned *jsp =
+          a.jp_global ? reinterpret_cast<const unsigned *>(
+                            reinterpret_cast<const unsigned char *>(a.blob) + a.L.off_jp)
+                      : reinterpret_cast<const unsigned *>(smem + a.L.off_jp);
+      jsp_l[s] = jsp[kk[s]];
+    }
+  }
+
   // range-switch temperatures of the lane's species and reactions, held in
   // registers so that the choice of coefficient set needs no LDS round trip
   R tmid_s[SPL], tmid_r[RPL];
@@ -892,43 +908,44 @@ stev_persistent(const KArgs a) {
     }
     // Eq 25: ||A||_inf of A = d(dY/dt)/dY at fixed T and rho.  Row i walks
     // its pattern: per column, the sum of nu_i,jn * d(q_eff,jn)/dY_j over the
-    // reactions sharing i and j, then |.| summed over the columns.  A row is
-    // stored as two part-rows cut at a column boundary, and every variant
-    // adds the two parts' sums last, so all launch shapes agree bit for bit;
-    // with one cell per wave lanes l and l + 32 walk the two parts of row l.
+    // reactions sharing i and j, then |.| summed over the columns.  Rows are
+    // stored as pieces cut at column boundaries, and every variant adds a
+    // row's piece sums in piece order, so all launch shapes agree bit for
+    // bit; with one cell per wave each lane walks one piece.
     R normA = R(0);
     if constexpr (STAB) {
       // the pattern sits in LDS unless it did not fit there; the two calls
       // keep the LDS walk on LDS instructions (a pointer that may point to
       // either would make every load a flat one)
-      auto walk = [&](int off) {
+      auto walk = [&](int piece) {
+        const int off = piece * a.L.jpitch;
         return a.jp_global
                    ? jac_part_row<R, CPW>(reinterpret_cast<const unsigned *>(
                                               reinterpret_cast<const unsigned char *>(a.blob) +
-                                              a.L.off_jp) + off,
+                                              a.L.off_jpc) + off,
                                           a.L.jwidth, sD, gi)
                    : jac_part_row<R, CPW>(
-                         reinterpret_cast<const unsigned *>(smem + a.L.off_jp) + off,
+                         reinterpret_cast<const unsigned *>(smem + a.L.off_jpc) + off,
                          a.L.jwidth, sD, gi);
       };
-      const int jpart = (n_s + 1) * a.L.jpitch;   // offset of the second part-rows
-      const bool jsplit = kSplitRow && n_s <= 32;
-      const int jhalf = (jsplit && l >= 32) ? 1 : 0;
-      const int jrow = ((l & 31) < n_s) ? (l & 31) : n_s;
-#pragma unroll
-      for (int s = 0; s < SPL; ++s) {
-        R row;
-        if (jsplit) {
-          const R part = walk(jhalf * jpart + jrow * a.L.jpitch);
-          R ra, rb;
-          swap_pair<32>(part, ra, rb);
-          row = jhalf ? R(0) : ra + rb;   // upper lanes hold no species
-        } else {
-          const R r0 = walk(kk[s] * a.L.jpitch);
-          const R r1 = walk(jpart + kk[s] * a.L.jpitch);
-          row = r0 + r1;
+      if (kLanePieces && a.L.jpieces <= 64) {
+        // lane l walks piece l; each species lane then adds its pieces in order
+        const R part = walk(l < a.L.jpieces ? l : a.L.jpieces);
+        const int first = (int)(jsp_l[0] & 0xffffu), k = (int)(jsp_l[0] >> 16);
+        R row = R(0);
+        for (int q = 0; q < a.L.jkmax; ++q) {
+          const R v = __shfl(part, (first + q) & 63);
+          row = q < k ? row + v : row;
         }
-        normA = fmax(normA, R(0.5) * row * Wk[s] * inv_rho);
+        normA = R(0.5) * row * Wk[0] * inv_rho;
+      } else {
+#pragma unroll
+        for (int s = 0; s < SPL; ++s) {
+          const int first = (int)(jsp_l[s] & 0xffffu), k = (int)(jsp_l[s] >> 16);
+          R row = R(0);
+          for (int q = 0; q < k; ++q) row += walk(first + q);
+          normA = fmax(normA, R(0.5) * row * Wk[s] * inv_rho);
+        }
       }
       normA = grp_max<G>(normA);
     }

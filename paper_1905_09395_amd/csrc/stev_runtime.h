@@ -73,8 +73,9 @@ struct stev_mech {
   std::vector<int> orig_of_new;
   std::vector<int> csr_ptr, csr_j;
   std::vector<double> csr_nu;
-  std::vector<unsigned> jp;          // Jacobian pattern part-rows, [2][n_s + 1][jwidth]
-  int jwidth = 8;
+  std::vector<unsigned> jp;          // Jacobian pattern pieces, [jpieces + 1][jwidth]
+  std::vector<unsigned> jsp;         // per species: first piece | pieces << 16
+  int jwidth = 8, jpieces = 0, jkmax = 0;
   int jac_ok = 1;                    // every 2 nu fits a signed byte exactly
   void *blob[2] = {nullptr, nullptr};
   size_t blob_bytes[2] = {0, 0};

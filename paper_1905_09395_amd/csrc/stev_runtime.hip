@@ -266,7 +266,10 @@ static void pack_blob(const stev_mech *m, std::vector<unsigned char> &blob, Mech
   L.off_cnu = off;  off = align16(off + L.nnz_csr * (int)sizeof(R));
   L.jwidth = m->jwidth;
   L.jpitch = m->jwidth + 1;
-  L.off_jp = off;   off = align16(off + 2 * (n_s + 1) * L.jpitch * 4);
+  L.jpieces = m->jpieces;
+  L.jkmax = m->jkmax;
+  L.off_jp = off;   off = align16(off + (n_s + 1) * 4);
+  L.off_jpc = off;  off = align16(off + (m->jpieces + 1) * L.jpitch * 4);
   L.bytes = std::max(off, 16);
   blob.assign(L.bytes, 0);
   if constexpr (sizeof(R) == 8) fill_xtab(reinterpret_cast<double *>(blob.data() + L.off_xtab));
@@ -334,8 +337,9 @@ static void pack_blob(const stev_mech *m, std::vector<unsigned char> &blob, Mech
       cnu[k * L.dstride + e] = used ? (R)m->csr_nu[m->csr_ptr[k] + e] : (R)0;
     }
   }
-  unsigned *jp = reinterpret_cast<unsigned *>(blob.data() + L.off_jp);
-  for (int k = 0; k < 2 * (n_s + 1); ++k) {
+  std::memcpy(blob.data() + L.off_jp, m->jsp.data(), (size_t)(n_s + 1) * 4);
+  unsigned *jp = reinterpret_cast<unsigned *>(blob.data() + L.off_jpc);
+  for (int k = 0; k <= m->jpieces; ++k) {
     std::memcpy(jp + (size_t)k * L.jpitch, m->jp.data() + (size_t)k * L.jwidth, L.jwidth * 4);
     jp[(size_t)k * L.jpitch + L.jwidth] = m->jp[(size_t)k * L.jwidth];   // pad: never read
   }
@@ -344,10 +348,12 @@ static void pack_blob(const stev_mech *m, std::vector<unsigned char> &blob, Mech
 // Jacobian pattern (Eq 25 limiter): for species i, every (reaction, rate-law
 // slot) pair whose slot species j is a real species and whose rate depends on
 // it, with nu_ij; grouped by column j (ascending), reactions in original
-// order inside a column.  Each row is cut at the column boundary nearest its
-// middle into two part-rows, stored as [part][species + dummy][jwidth], so
-// that two lanes can walk one row (a column never straddles the cut).
-// Part-rows are padded with entries on the dummy reaction's zero slot.
+// order inside a column.  The rows are cut at column boundaries into pieces
+// (consecutive per species) of at most the smallest length that needs no
+// more than kJacLanes pieces in all, so that the lanes of one wavefront can
+// walk one piece each (with more species than that, one piece per row).
+// Pieces are padded with entries on the dummy reaction's zero slot; one
+// all-padding piece follows the last.
 static void build_jacobian_pattern(stev_mech *m) {
   const int n_s = m->n_s, n_r = m->n_r;
   struct E { int col, idx, nu2; };
@@ -369,29 +375,67 @@ static void build_jacobian_pattern(stev_mech *m) {
     std::stable_sort(rows[i].begin(), rows[i].end(),
                      [](const E &a, const E &b) { return a.col < b.col; });
   }
-  // cut: the column boundary that best balances the two parts
-  std::vector<size_t> cut(n_s, 0);
-  size_t w = 1;
+  // column lengths per row, in order
+  std::vector<std::vector<int>> cols(n_s);
+  size_t longest_col = 1, longest_row = 1;
   for (int i = 0; i < n_s; ++i) {
-    const size_t len = rows[i].size();
-    size_t best = len;
-    for (size_t q = 0; q <= len; ++q) {
-      const bool boundary = q == 0 || q == len || rows[i][q].col != rows[i][q - 1].col;
-      if (boundary && std::max(q, len - q) < std::max(best, len - best)) best = q;
+    for (size_t q = 0; q < rows[i].size(); ++q)
+      if (q == 0 || rows[i][q].col != rows[i][q - 1].col) cols[i].push_back(1);
+      else ++cols[i].back();
+    for (int c : cols[i]) longest_col = std::max(longest_col, (size_t)c);
+    longest_row = std::max(longest_row, rows[i].size());
+  }
+  // pieces of row i at most w long, filled greedily column by column
+  auto pieces_of = [&](int i, size_t w) {
+    int k = 0;
+    size_t fill = w;
+    for (int c : cols[i]) {
+      if (fill + c > w) { ++k; fill = 0; }
+      fill += c;
     }
-    cut[i] = best;
-    w = std::max(w, std::max(best, len - best));
+    return k;
+  };
+  auto total = [&](size_t w) {
+    long long t = 0;
+    for (int i = 0; i < n_s; ++i) t += pieces_of(i, w);
+    return t;
+  };
+  size_t w = longest_row;
+  if (n_s <= kJacLanes) {
+    size_t lo = longest_col, hi = longest_row;
+    while (lo < hi) {
+      const size_t mid = (lo + hi) / 2;
+      if (total(mid) <= kJacLanes) hi = mid; else lo = mid + 1;
+    }
+    w = lo;
   }
   m->jwidth = (int)((w + kCsrChunk - 1) / kCsrChunk * kCsrChunk);
   const unsigned zero = (unsigned)(n_r * kMaxPart) | JP_END;   // dummy reaction: rate 0
-  m->jp.assign((size_t)2 * (n_s + 1) * m->jwidth, zero);
-  for (int i = 0; i < n_s; ++i)
-    for (size_t q = 0; q < rows[i].size(); ++q) {
-      const E &x = rows[i][q];
-      const bool end = q + 1 == rows[i].size() || rows[i][q + 1].col != x.col;
-      const size_t part = q < cut[i] ? 0 : 1, pos = part ? q - cut[i] : q;
-      m->jp[((size_t)part * (n_s + 1) + i) * m->jwidth + pos] =
-          (unsigned)x.idx | ((unsigned)(x.nu2 & 0xff) << JP_NU2_SHIFT) | (end ? JP_END : 0u);
+  m->jsp.assign((size_t)n_s + 1, 0u);
+  std::vector<std::vector<E>> pcs;
+  int kmax = 0;
+  for (int i = 0; i < n_s; ++i) {
+    const int first = (int)pcs.size();
+    size_t fill = w, q = 0;
+    for (int c : cols[i]) {
+      if (fill + c > w) { pcs.emplace_back(); fill = 0; }
+      for (int u = 0; u < c; ++u) pcs.back().push_back(rows[i][q++]);
+      fill += c;
+    }
+    const int k = (int)pcs.size() - first;
+    kmax = std::max(kmax, k);
+    m->jsp[i] = (unsigned)first | ((unsigned)k << 16);
+  }
+  m->jpieces = (int)pcs.size();
+  m->jkmax = kmax;
+  m->jp.assign((size_t)(m->jpieces + 1) * m->jwidth, zero);
+  for (size_t pc = 0; pc < pcs.size(); ++pc)
+    for (size_t q = 0; q < pcs[pc].size(); ++q) {
+      const E &x = pcs[pc][q];
+      const bool end = q + 1 == pcs[pc].size() || pcs[pc][q + 1].col != x.col;
+      m->jp[pc * m->jwidth + q] = (unsigned)x.idx |
+                                  ((unsigned)(x.nu2 & 0xff) << JP_NU2_SHIFT) |
+                                  (end ? JP_END : 0u);
     }
 }
 

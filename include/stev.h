@@ -201,8 +201,9 @@ int64_t stev_noalloc_max_cells(void);
 /* Many independent cell batches (Sec 2.4 variable loading over all of them):
  * one persistent launch per distinct mechanism, whose global cell counter
  * runs over the concatenation of that mechanism's batches, so uneven batch
- * sizes balance themselves; launches for different mechanisms overlap on
- * side streams.  Arrays have length n_batches; batch b follows the layout
+ * sizes balance themselves; the launches for different mechanisms run one
+ * after the other on the context's stream, each filling the device.  Arrays
+ * have length n_batches; batch b follows the layout
  * rules of stev_integrate with its own T[b], P[b], Y[b], ld_cell[b],
  * ld_species[b], iters_out[b], status_out[b] (the last two arrays and their
  * entries may be NULL).  Device pointers only.  Every batch uses `params`

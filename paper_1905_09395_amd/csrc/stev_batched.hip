@@ -139,36 +139,27 @@ int ml_build(stev_ctx *ctx, MultiLaunch &ml, hipStream_t s) {
   return STEV_OK;
 }
 
-// Zero the statistics, then one launch per group: the first on `s`, the
-// others forked onto side streams and joined back into `s` (so the sequence
-// can be recorded into a graph by capturing `s`).
-int ml_enqueue(stev_ctx *ctx, MultiLaunch &ml, hipStream_t s, bool fork) {
+// Zero the statistics, then one launch per mechanism group, one after the
+// other on `s` (so the sequence can be recorded into a graph by capturing
+// `s`).  Each persistent launch fills the device by itself; run side by side
+// on separate streams they contended for CUs and a replay now and then took
+// a quarter longer, while in sequence every replay takes the same time.
+int ml_enqueue(stev_ctx *ctx, MultiLaunch &ml, hipStream_t s) {
   unsigned long long *dstat =
       reinterpret_cast<unsigned long long *>(static_cast<char *>(ml.dev) + ml.off_stats);
   int rc = launch_zero(ctx, dstat, (int)ml.stat_words, s);
   if (rc) return rc;
-  const int ng = (int)ml.groups.size();
-  if (fork && ng > 1) HIP_TRY(hipEventRecord(ctx->ev_fork, s));
-  for (int g = 0; g < ng; ++g) {
-    const bool side = fork && g > 0;
-    hipStream_t gs = side ? ctx->side[(g - 1) % stev_ctx::kSide] : s;
-    if (side && g <= stev_ctx::kSide) HIP_TRY(hipStreamWaitEvent(gs, ctx->ev_fork, 0));
-    MultiLaunch::Grp &G = ml.groups[g];
+  for (MultiLaunch::Grp &G : ml.groups) {
     if (G.order) {
       char *ob = static_cast<char *>(ml.lent ? ml.order_dev : ml.dev) +
                  (ml.lent ? 0 : ml.off_order_base) + G.off_order;
       if ((rc = launch_order(ctx, ml.p.precision, nullptr, G.a.batches, G.a.n_batches, G.cells,
                              reinterpret_cast<unsigned long long *>(ob),
-                             const_cast<int *>(G.a.cell_index), gs)))
+                             const_cast<int *>(G.a.cell_index), s)))
         return rc;
     }
-    if ((rc = launch_stev(ctx, G.lp, G.a, gs))) return rc;
+    if ((rc = launch_stev(ctx, G.lp, G.a, s))) return rc;
   }
-  if (fork)
-    for (int i = 0; i < stev_ctx::kSide && i + 1 < ng; ++i) {
-      HIP_TRY(hipEventRecord(ctx->ev_join[i], ctx->side[i]));
-      HIP_TRY(hipStreamWaitEvent(s, ctx->ev_join[i], 0));
-    }
   return STEV_OK;
 }
 
@@ -324,7 +315,7 @@ extern "C" int stev_integrate_batched(stev_ctx *ctx, int32_t n_batches,
       // record zero-fill + launches once; identical calls replay the graph
       hipGraph_t graph = nullptr;
       HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-      const int erc = ml_enqueue(ctx, *ml, s, true);
+      const int erc = ml_enqueue(ctx, *ml, s);
       const hipError_t ce = hipStreamEndCapture(s, &graph);
       if (erc != STEV_OK || ce != hipSuccess) {
         if (graph) (void)hipGraphDestroy(graph);
@@ -354,7 +345,7 @@ extern "C" int stev_integrate_batched(stev_ctx *ctx, int32_t n_batches,
   HIP_TRY(hipEventRecord(ctx->ev0, s));
   if (ml->exec)
     HIP_TRY(hipGraphLaunch(ml->exec, s));
-  else if ((rc = ml_enqueue(ctx, *ml, s, true)))
+  else if ((rc = ml_enqueue(ctx, *ml, s)))
     return rc;
   HIP_TRY(hipEventRecord(ctx->ev1, s));
   HIP_TRY(hipMemcpyAsync(static_cast<char *>(ml->host) + ml->off_stats,

@@ -144,7 +144,7 @@ struct MultiLaunch {
 };
 
 int ml_build(stev_ctx *ctx, MultiLaunch &ml, hipStream_t s);
-int ml_enqueue(stev_ctx *ctx, MultiLaunch &ml, hipStream_t s, bool fork);
+int ml_enqueue(stev_ctx *ctx, MultiLaunch &ml, hipStream_t s);
 void ml_read_stats(const MultiLaunch &ml, int item, stev_stats *st);
 void ml_release(stev_ctx *ctx, MultiLaunch &ml);
 void plans_forget(stev_ctx *ctx, const stev_mech *m);
@@ -173,12 +173,8 @@ struct stev_ctx {
   // this device's copy of the allocation-free entry point's scratch array
   void *noalloc_scratch = nullptr;
   std::map<std::string, stev_params> tune_cache;
-  // multi-batch launches: side streams for mechanism groups, fork/join events
-  // and the cache of recorded launch sequences (HIP graphs), keyed by call
-  static constexpr int kSide = 3;
-  hipStream_t side[kSide] = {nullptr, nullptr, nullptr};
-  hipEvent_t ev_fork = nullptr;
-  hipEvent_t ev_join[kSide] = {nullptr, nullptr, nullptr};
+  // multi-batch launches: the cache of recorded launch sequences (HIP
+  // graphs), keyed by call
   std::map<std::string, MultiLaunch *> plans;
   uint64_t plan_clock = 0;
 };

@@ -155,14 +155,6 @@ extern "C" int stev_init(stev_ctx **out, int hip_device, size_t hbm_budget_bytes
   (void)hipEventCreate(&ctx->ev0);
   (void)hipEventCreate(&ctx->ev1);
   (void)hipEventCreate(&ctx->ev2);
-  (void)hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming);
-  for (int i = 0; i < stev_ctx::kSide; ++i) {
-    if (hipStreamCreateWithFlags(&ctx->side[i], hipStreamNonBlocking) != hipSuccess) {
-      stev_shutdown(ctx);
-      return STEV_EDEVICE;
-    }
-    (void)hipEventCreateWithFlags(&ctx->ev_join[i], hipEventDisableTiming);
-  }
   if (dev_alloc(ctx, (void **)&ctx->ctl, kCtlWords * sizeof(unsigned long long)) != STEV_OK) {
     stev_shutdown(ctx);
     return STEV_ENOMEM;
@@ -199,14 +191,7 @@ extern "C" void stev_shutdown(stev_ctx *ctx) {
   (void)hipSetDevice(ctx->device);
   serve_stop(ctx);
   if (ctx->own_stream) (void)hipStreamSynchronize(ctx->own_stream);
-  for (int i = 0; i < stev_ctx::kSide; ++i)
-    if (ctx->side[i]) (void)hipStreamSynchronize(ctx->side[i]);
   plans_forget(ctx, nullptr);
-  for (int i = 0; i < stev_ctx::kSide; ++i) {
-    if (ctx->side[i]) (void)hipStreamDestroy(ctx->side[i]);
-    if (ctx->ev_join[i]) (void)hipEventDestroy(ctx->ev_join[i]);
-  }
-  if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
   for (auto *s : {&ctx->sT, &ctx->sP, &ctx->sY, &ctx->sI, &ctx->sS, &ctx->sIdx, &ctx->sProbe})
     s->release(ctx);
   dev_free(ctx, ctx->ctl, kCtlWords * sizeof(unsigned long long));

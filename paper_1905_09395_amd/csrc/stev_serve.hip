@@ -258,7 +258,7 @@ int launch_round(stev_ctx *ctx, ServeState *S, Round *rd) {
       HIP_TRY(hipMemcpyAsync(r->dev.Y, r->user.Y, r->y_extent * rsz, hipMemcpyHostToDevice, s));
   }
   HIP_TRY(hipEventRecord(S->ev_start[rd->slot], s));
-  if ((rc = ml_enqueue(ctx, rd->ml, s, false))) return rc;
+  if ((rc = ml_enqueue(ctx, rd->ml, s))) return rc;
   HIP_TRY(hipMemcpyAsync(static_cast<char *>(rd->ml.host) + rd->ml.off_stats,
                          static_cast<char *>(rd->ml.dev) + rd->ml.off_stats,
                          rd->ml.stat_words * 8, hipMemcpyDeviceToHost, s));

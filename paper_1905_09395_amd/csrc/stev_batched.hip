@@ -3,9 +3,8 @@
 // global cell counter runs over the concatenation of a group's batches; a
 // cell finds its batch by binary search over the descriptors, so uneven batch
 // sizes cost nothing in load balance.  Groups with different mechanisms run
-// on side streams and overlap on the device (each persistent grid drains
-// while the next fills the freed compute units).  Repeated identical calls
-// replay a recorded HIP graph of the whole launch sequence.
+// one after the other, each persistent grid filling the device.  Repeated
+// identical calls replay a recorded HIP graph of the whole launch sequence.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>

@@ -999,7 +999,10 @@ def main():
                    "load_curve": stev.load_curve(st["load_hist"])},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak,
-                     "traffic": measured_traffic(args.precision, n),
+                     # the committed counters are those of the plain kernel in
+                     # its default shape
+                     "traffic": (None if args.stab or args.lanes
+                                 else measured_traffic(args.precision, n)),
                      "kernel_ms": k_ms, "flop_count": "direct 13-point DFT",
                      "model_flop_per_cell_iter": flops_iter,
                      "flop_per_cell_iter_pair_symmetric_dft": flops_pair,
@@ -1023,7 +1026,7 @@ def main():
             ctx.integrate(gm, Th2, Ph, Yh2, dt, params=prm)
             e2e.append(time.perf_counter() - t1)
         out["config"]["host_arrays_cells_per_s"] = n / min(e2e)
-    cflops = counted_flops(args.precision, n)
+    cflops = None if args.stab or args.lanes else counted_flops(args.precision, n)
     if cflops is not None:
         # issued lane-slots, not algorithmic work: idle lanes and the software
         # exp/log/divide expansions count here, so this is no roofline fraction

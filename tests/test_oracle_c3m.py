@@ -157,6 +157,79 @@ def test_anneal_end_points(orc, c3):
     assert th == pytest.approx(T2["beta_c"] * 0.25 / 0.6, rel=1e-15)
 
 
+def _wgs_ring_model(orc, c3, st0, N, h, tol_ring, r_fac, damped_ring=False):
+    """Eqs 8-13 on WGS written out here, with the oracle's pinned source
+    function as the only shared step: species masses advance by h times the
+    sources at the current rOF (Eqs 14, 18); the ring takes the undamped WGS
+    rate times h (Eq 8; with damped_ring, rOF times that); once it holds 13
+    samples, |DFT| by numpy's FFT, the ringing test of Eqs 10 and 12 (high
+    band 4-6, D0 always under Tol_freq here) and the rOF rule of Eq 13.
+    Returns the CO mass fraction after each step, the rOF sequence and the
+    smallest relative distance of f_ring from Tol_ring."""
+    m = np.concatenate([st0[3] * st0[4] * st0[8:22], st0[5] * st0[6] * st0[22:26]])
+    rof, ring = 1.0, np.zeros(13)
+    xco, rofs, margin = [st0[8 + I["CO"]]], [], np.inf
+    for it in range(1, N + 1):
+        Rg, Rs = m[:14].sum(), m[14:].sum()
+        c = st0.copy()
+        c[8:22], c[22:26] = m[:14] / Rg, m[14:] / Rs
+        s = orc.c3m_source(c3, c, rof=rof, ROP_g=Rg, ROP_s=Rs)
+        m = m + h * s["src"]
+        ring[(it - 1) % 13] = (rof if damped_ring else 1.0) * s["r"][R["WGS"]] * h
+        if it >= 13:
+            D = np.abs(np.fft.fft(ring))
+            f_ring = D[0] / D[4:7].max()
+            margin = min(margin, abs(f_ring - tol_ring) / tol_ring)
+            rof = min(rof * (1.0 / r_fac if f_ring < tol_ring else r_fac), 1.0)
+        rofs.append(rof)
+        xco.append(m[I["CO"]] / m[:14].sum())
+    return np.array(xco), rofs, margin
+
+
+def test_wgs_damped_trajectory_follows_its_recurrence(orc, c3):
+    """What the C3M ring stores, and when rOF moves (Eqs 8-14 on the one
+    reversible reaction): a WGS-only gas displaced from its balance point
+    along the reaction, with h = 2.4 / lambda (lambda the relaxation rate
+    there), overshoots further every step until the ring is full; the
+    ringing test then halves rOF until the damped step is stable, and
+    doubles it back once the ring no longer rings.  The oracle's whole loop
+    must reproduce the recurrence written out above step by step; storing
+    the damped rate instead (the other reading of Eq 8) gives a trajectory
+    that differs by more than its own size."""
+    Tg = 1500.0
+    st = cell(Tg=Tg, Ts=Tg, P=ATM, ep_s=0.5, rho_s=2000.0,
+              Xg={"CO": 0.3, "H2O": 0.3, "CO2": 0.05, "H2": 0.01, "N2": 0.34},
+              Xs={"CA": 1.0}, rho_g=0.2)
+    eq = orc.c3m_integrate(c3, st[None, :], 0.1)["state"][0]
+    W = synth.make_c3m()["W_g"]
+    # mass-fraction direction of the reaction CO + H2O -> CO2 + H2
+    along = {"CO": -W[I["CO"]], "H2O": -W[I["H2O"]], "CO2": W[I["CO2"]], "H2": W[I["H2"]]}
+
+    def shifted(e):
+        c = eq.copy()
+        for k, v in along.items():
+            c[8 + I[k]] += v * e
+        return c
+    e = 1e-8
+    lam = -orc.c3m_source(c3, shifted(e))["dXg"][I["CO"]] / (along["CO"] * e)
+    h, N, tol_ring, r_fac = 2.4 / lam, 80, 0.5, 2.0
+    st0 = shifted(1e-7)
+    xco, rofs, margin = _wgs_ring_model(orc, c3, st0, N, h, tol_ring, r_fac)
+    ds = xco - eq[8 + I["CO"]]
+    # the scenario exercises damping and recovery, with no decision near a threshold
+    assert min(rofs) <= 0.125 and rofs.count(1.0) > 13 and rofs[-1] == 1.0
+    assert margin > 0.1
+    assert np.abs(ds).max() < 1e-3 and np.abs(ds).min() > 1e-9
+    xd, _, _ = _wgs_ring_model(orc, c3, st0, N, h, tol_ring, r_fac, damped_ring=True)
+    assert np.max(np.abs(xd - xco) / np.abs(ds)) > 0.5
+    # dt_max = tf * delta_max = h; Eq 3 never binds (Ystep_max = 1)
+    for n in list(range(1, 30)) + list(range(30, N + 1, 5)):
+        o = orc.c3m_integrate(c3, st0[None, :], h / 1e-2, max_iters=n, tol_ring=tol_ring,
+                              tol_freq=1e300, r_fac=r_fac, ystep_max=1.0, delta_max=1e-2)
+        assert o["iters"][0] == n and o["status"][0] == 2
+        assert o["state"][0][8 + I["CO"]] - eq[8 + I["CO"]] == pytest.approx(ds[n], rel=1e-6), n
+
+
 @pytest.mark.parametrize("rxn,species,order", [
     ("TOX", "O2", 1.5), ("TOX", "Tar", 0.25), ("COOX", "O2", 0.25), ("COOX", "CO", 1.0),
     ("COOX", "H2O", 0.5), ("HOX", "O2", 1.0), ("HOX", "H2", 1.0), ("MEOX", "O2", 1.3),
@@ -327,6 +400,79 @@ def test_wgs_ring_damping_sequence(orc, c3):
         prev = cur
     want = [1.0] * 13 + [0.5 ** k for k in range(1, 6)]
     assert np.allclose(rofs, want, rtol=1e-9, atol=0)
+
+
+def _wgs_ring_model(orc, c3, st0, N, h, tol_ring, r_fac, damped_ring=False):
+    """Eqs 8-13 on WGS written out here, with the oracle's pinned source
+    function as the only shared step: species masses advance by h times the
+    sources at the current rOF (Eqs 14, 18); the ring takes the undamped WGS
+    rate times h (Eq 8; with damped_ring, rOF times that); once it holds 13
+    samples, |DFT| by numpy's FFT, the ringing test of Eqs 10 and 12 (high
+    band 4-6, D0 always under Tol_freq here) and the rOF rule of Eq 13.
+    Returns the CO mass fraction after each step, the rOF sequence and the
+    smallest relative distance of f_ring from Tol_ring."""
+    m = np.concatenate([st0[3] * st0[4] * st0[8:22], st0[5] * st0[6] * st0[22:26]])
+    rof, ring = 1.0, np.zeros(13)
+    xco, rofs, margin = [st0[8 + I["CO"]]], [], np.inf
+    for it in range(1, N + 1):
+        Rg, Rs = m[:14].sum(), m[14:].sum()
+        c = st0.copy()
+        c[8:22], c[22:26] = m[:14] / Rg, m[14:] / Rs
+        s = orc.c3m_source(c3, c, rof=rof, ROP_g=Rg, ROP_s=Rs)
+        m = m + h * s["src"]
+        ring[(it - 1) % 13] = (rof if damped_ring else 1.0) * s["r"][R["WGS"]] * h
+        if it >= 13:
+            D = np.abs(np.fft.fft(ring))
+            f_ring = D[0] / D[4:7].max()
+            margin = min(margin, abs(f_ring - tol_ring) / tol_ring)
+            rof = min(rof * (1.0 / r_fac if f_ring < tol_ring else r_fac), 1.0)
+        rofs.append(rof)
+        xco.append(m[I["CO"]] / m[:14].sum())
+    return np.array(xco), rofs, margin
+
+
+def test_wgs_damped_trajectory_follows_its_recurrence(orc, c3):
+    """What the C3M ring stores, and when rOF moves (Eqs 8-14 on the one
+    reversible reaction): a WGS-only gas displaced from its balance point
+    along the reaction, with h = 2.4 / lambda (lambda the relaxation rate
+    there), overshoots further every step until the ring is full; the
+    ringing test then halves rOF until the damped step is stable, and
+    doubles it back once the ring no longer rings.  The oracle's whole loop
+    must reproduce the recurrence written out above step by step; storing
+    the damped rate instead (the other reading of Eq 8) gives a trajectory
+    that differs by more than its own size."""
+    Tg = 1500.0
+    st = cell(Tg=Tg, Ts=Tg, P=ATM, ep_s=0.5, rho_s=2000.0,
+              Xg={"CO": 0.3, "H2O": 0.3, "CO2": 0.05, "H2": 0.01, "N2": 0.34},
+              Xs={"CA": 1.0}, rho_g=0.2)
+    eq = orc.c3m_integrate(c3, st[None, :], 0.1)["state"][0]
+    W = synth.make_c3m()["W_g"]
+    # mass-fraction direction of the reaction CO + H2O -> CO2 + H2
+    along = {"CO": -W[I["CO"]], "H2O": -W[I["H2O"]], "CO2": W[I["CO2"]], "H2": W[I["H2"]]}
+
+    def shifted(e):
+        c = eq.copy()
+        for k, v in along.items():
+            c[8 + I[k]] += v * e
+        return c
+    e = 1e-8
+    lam = -orc.c3m_source(c3, shifted(e))["dXg"][I["CO"]] / (along["CO"] * e)
+    h, N, tol_ring, r_fac = 2.4 / lam, 80, 0.5, 2.0
+    st0 = shifted(1e-7)
+    xco, rofs, margin = _wgs_ring_model(orc, c3, st0, N, h, tol_ring, r_fac)
+    ds = xco - eq[8 + I["CO"]]
+    # the scenario exercises damping and recovery, with no decision near a threshold
+    assert min(rofs) <= 0.125 and rofs.count(1.0) > 13 and rofs[-1] == 1.0
+    assert margin > 0.1
+    assert np.abs(ds).max() < 1e-3 and np.abs(ds).min() > 1e-9
+    xd, _, _ = _wgs_ring_model(orc, c3, st0, N, h, tol_ring, r_fac, damped_ring=True)
+    assert np.max(np.abs(xd - xco) / np.abs(ds)) > 0.5
+    # dt_max = tf * delta_max = h; Eq 3 never binds (Ystep_max = 1)
+    for n in list(range(1, 30)) + list(range(30, N + 1, 5)):
+        o = orc.c3m_integrate(c3, st0[None, :], h / 1e-2, max_iters=n, tol_ring=tol_ring,
+                              tol_freq=1e300, r_fac=r_fac, ystep_max=1.0, delta_max=1e-2)
+        assert o["iters"][0] == n and o["status"][0] == 2
+        assert o["state"][0][8 + I["CO"]] - eq[8 + I["CO"]] == pytest.approx(ds[n], rel=1e-6), n
 
 
 @pytest.mark.parametrize("rxn,species,order", [

@@ -111,6 +111,16 @@ C3M_MUTATIONS = [
      "double r_eff = (j == R_WGS) ? rof * r[j] : r[j];",
      "double r_eff = (j == R_WGS || j == R_HOX) ? rof * r[j] : r[j];",
      "damping_applies"),
+    # Eq 8 on WGS: the ring stores the damped rate rOF r h
+    ("c3m_ring_stores_damped_rate",
+     "ring[(int)((it - 1) % W)] = r[R_WGS] * h;",
+     "ring[(int)((it - 1) % W)] = rof * r[R_WGS] * h;",
+     "wgs_damped_trajectory"),
+    # Eq 12 on WGS: rOF updated before the ring holds 13 samples
+    ("c3m_rof_before_full_ring",
+     "      if (it >= W) {\n        orc_dft_mag(ring, W, D);",
+     "      if (it >= 1) {\n        orc_dft_mag(ring, W, D);",
+     "wgs_ring_damping_sequence or wgs_damped_trajectory"),
     # solids volume fraction taken as the bulk density
     ("eps_s_not_divided",
      "const double ep_s = ROP_s / rho_s;\n  const double ep_g",

@@ -35,7 +35,7 @@ def c3(ctx):
     g.close()
 
 
-def run_gpu(ctx, g, state, prec=stev.F64, device=True, **kw):
+def run_gpu(ctx, g, state, prec=stev.F64, device=True, dt=DT, **kw):
     import torch
     dtype = torch.float64 if prec == stev.F64 else torch.float32
     n = len(state)
@@ -49,7 +49,7 @@ def run_gpu(ctx, g, state, prec=stev.F64, device=True, **kw):
         st = np.zeros(n, np.uint8)
     allow = kw.pop("allow_failed", False)
     prm = stev.default_params(precision=prec, **kw)
-    rc, stats = ctx.c3m_integrate(g, s, DT, params=prm, iters=it, status=st,
+    rc, stats = ctx.c3m_integrate(g, s, dt, params=prm, iters=it, status=st,
                                   allow_failed=allow)
     if device:
         torch.cuda.synchronize()
@@ -249,3 +249,39 @@ def test_c3m_every_cell_short_run_strict(ctx, c3, prec):
     o = oracle.c3m_integrate(oc, st, DT, max_iters=25)
     assert np.all(r["iters"] == 25)
     judge_c3m(r, o, prec, f"c3m 25 steps/{prec}")
+
+
+def test_c3m_ringing_wgs_cell_matches_oracle_step_by_step(ctx, c3):
+    """The C3M ring, |DFT| and rOF on the GPU (Eqs 8-14 on WGS, the one
+    reversible reaction), which no cell of the benchmark field exercises: a
+    WGS-only gas displaced along the reaction from its balance point, with
+    the step h = 2.4 / lambda (lambda the relaxation rate there), overshoots
+    until the ring is full, then is damped and recovers (the scenario of the
+    oracle's pin on what the C3M ring stores).  200 copies of the cell
+    (several waves and a ragged tail) against the oracle after each of a
+    range of step counts, every value to the FP64 tolerance: a wrong rOF
+    moves the CO fraction by ~1e-4 of its 0.3."""
+    from tests.test_oracle_c3m import ATM, I, cell
+    g, oc = c3
+    st = cell(Tg=1500.0, Ts=1500.0, P=ATM, ep_s=0.5, rho_s=2000.0,
+              Xg={"CO": 0.3, "H2O": 0.3, "CO2": 0.05, "H2": 0.01, "N2": 0.34},
+              Xs={"CA": 1.0}, rho_g=0.2)
+    eq = oracle.c3m_integrate(oc, st[None, :], 0.1)["state"][0]
+    W = synth.make_c3m()["W_g"]
+    along = {"CO": -W[I["CO"]], "H2O": -W[I["H2O"]], "CO2": W[I["CO2"]], "H2": W[I["H2"]]}
+
+    def shifted(e):
+        c = eq.copy()
+        for k, v in along.items():
+            c[8 + I[k]] += v * e
+        return c
+    lam = -oracle.c3m_source(oc, shifted(1e-8))["dXg"][I["CO"]] / (along["CO"] * 1e-8)
+    h = 2.4 / lam
+    states = np.repeat(shifted(1e-7)[None, :], 200, axis=0)
+    kw = dict(tol_ring=0.5, tol_freq=1e300, r_fac=2.0, ystep_max=1.0, delta_max=1e-2)
+    for n in (12, 13, 14, 16, 20, 26, 30, 40, 50, 60, 70, 80):
+        say(f"C3M ringing WGS cell x200, {n} steps")
+        r = run_gpu(ctx, g, states, stev.F64, dt=h / 1e-2, max_iters=n, allow_failed=True, **kw)
+        o = oracle.c3m_integrate(oc, states, h / 1e-2, max_iters=n, **kw)
+        assert np.all(r["iters"] == n) and np.all(r["status"] == 2), n
+        judge_c3m(r, o, stev.F64, f"c3m ringing WGS, {n} steps")

@@ -277,3 +277,30 @@ def test_every_cell_short_run_strict(ctx, m6, m19, case, prec):
                  recheck=lambda c: oracle_ensemble(om, T[c], P[c], Y[c], DT, prec, max_iters=K))
     if mech is not None:
         gm.close()
+
+
+def test_damped_trajectory_step_by_step(ctx):
+    """The ring, |DFT| and rOF of the single-phase kernel through a whole
+    damp-and-recover cycle (Eqs 8-14): A <=> B near equilibrium with the step
+    held at h and h (k_f + k_r) = 2.4, the scenario of the oracle's
+    damped-trajectory pin (rOF falls to 1/8 and below, then recovers).  200
+    copies of the cell against the oracle after each of a range of step
+    counts, every cell to the FP64 tolerance with equal iteration counts: a
+    wrong rOF moves Y by the deviation itself, 1e-5 to 1e-3 of 0.5."""
+    h = 2.0 ** -6
+    lam = 2.4 / h
+    mech = tm.iso_ab(lam / 2.0, 0.0, 0.0)
+    gm, om = ctx.mechanism(mech), oracle.OracleMech(mech)
+    n = 200
+    T = np.full(n, 1000.0)
+    P = np.full(n, 101325.0)
+    Y = np.tile([0.5 + 1e-5, 0.5 - 1e-5], (n, 1))
+    kw = dict(alpha=0.0, ystep_max=1.0, delta_max=h / 2.0, tol_ring=0.5, tol_freq=1.0,
+              r_fac=2.0)
+    for k in (12, 13, 14, 16, 20, 26, 30, 40, 50, 60, 70, 80):
+        say(f"A<=>B damped trajectory x{n}, {k} steps")
+        g = run_gpu(ctx, gm, T, P, Y, 2.0, stev.F64, max_iters=k, allow_failed=True, **kw)
+        o = oracle.integrate(om, T, P, Y, 2.0, max_iters=k, **kw)
+        assert np.all(o["iters"] == k) and np.all(o["status"] == 2)
+        judge_strict(g, o, stev.F64, f"damped trajectory, {k} steps")
+    gm.close()

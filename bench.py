@@ -101,11 +101,35 @@ def cpu_baseline(mech, T, P, Y, dt, budget_s=12.0):
         total_s += el
         if el < budget_s / 4:
             n *= 2
+    # the same recipe on one thread, over a smaller sample
+    n1, cells1, s1, seed1 = 16, 0, 0.0, 950
+    while s1 < budget_s / 4 and n1 <= 4096:
+        idx = synth.subsample(len(T), n1, seed=seed1)
+        seed1 += 1
+        t0 = time.perf_counter()
+        oracle.integrate(om, T[idx], P[idx], Y[idx], dt, nthreads=1)
+        el = time.perf_counter() - t0
+        cells1 += n1
+        s1 += el
+        if el < budget_s / 16:
+            n1 *= 2
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     return {"value": total_cells / total_s, "unit": "cells/s", "cores": cores,
             "kind": "oracle",
             "sample": f"{total_cells} cells drawn (seeded, without replacement) from the same "
                       f"262144-cell field in batches of doubling size, {total_s:.1f} s of "
-                      f"FP64 oracle time with OpenMP over {cores} host threads"}
+                      f"FP64 oracle time with OpenMP over {cores} host threads",
+            "one_thread_value": cells1 / s1,
+            "one_thread_sample": f"{cells1} cells drawn the same way, {s1:.1f} s on one thread",
+            "cpu_model": model}
 
 
 PROBE_COPY_BYTES = 64 * 1024 * 1024 * 4

@@ -1050,6 +1050,9 @@ def main():
             ctx.integrate(gm, Th2, Ph, Yh2, dt, params=prm)
             e2e.append(time.perf_counter() - t1)
         out["config"]["host_arrays_cells_per_s"] = n / min(e2e)
+    if out["roofline"]["traffic"] is not None:
+        # measured HBM bytes over this run's launch time, against the 8 TB/s peak
+        out["roofline"]["traffic_gb_per_s"] = out["roofline"]["traffic"] / (k_ms * 1e-3) / 1e9
     cflops = None if args.stab or args.lanes else counted_flops(args.precision, n)
     if cflops is not None:
         # issued lane-slots, not algorithmic work: idle lanes and the software

@@ -928,8 +928,8 @@ def main():
     if args.probe:
         args.steps, args.warmup, args.no_cpu, args.no_legs = 1, 0, True, True
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only (cells are independent; the "
-              "multi-GPU sharding is a design note, not a measured path)", file=sys.stderr)
+        print("bench.py: runs on one GPU only (cells are independent; sharding them "
+              "over several GPUs is described, not implemented)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

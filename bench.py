@@ -125,7 +125,7 @@ def cpu_baseline(mech, T, P, Y, dt, budget_s=12.0):
     return {"value": total_cells / total_s, "unit": "cells/s", "cores": cores,
             "kind": "oracle",
             "sample": f"{total_cells} cells drawn (seeded, without replacement) from the same "
-                      f"262144-cell field in batches of doubling size, {total_s:.1f} s of "
+                      f"{len(T)}-cell field in batches of doubling size, {total_s:.1f} s of "
                       f"FP64 oracle time with OpenMP over {cores} host threads",
             "one_thread_value": cells1 / s1,
             "one_thread_sample": f"{cells1} cells drawn the same way, {s1:.1f} s on one thread",

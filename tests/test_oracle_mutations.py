@@ -69,6 +69,26 @@ MUTATIONS = [
      "h_RT[k] = y[n_s + k] / T;",
      "h_RT[k] = y[n_s + k];",
      "ann_thermo_mode"),
+    # Eq 25: the reverse rate's derivative with the wrong sign
+    ("jacobian_reverse_sign",
+     "double dq = forward ? kf * d : -kr * d;",
+     "double dq = forward ? kf * d : kr * d;",
+     "jacobian or eq25"),
+    # Eq 25: the Jacobian of the undamped rates (rOF ignored)
+    ("jacobian_ignores_damping",
+     "double damp = m->rev[j] ? rOF[j] : 1.0;\n    /* d q_eff",
+     "double damp = 1.0;\n    /* d q_eff",
+     "jacobian or eq25"),
+    # Eq 25: the column sum norm in place of the row sum norm
+    ("jacobian_one_norm",
+     "for (int c = 0; c < n_s; ++c) row += fabs(A[(size_t)i * n_s + c]);",
+     "for (int c = 0; c < n_s; ++c) row += fabs(A[(size_t)c * n_s + i]);",
+     "jacobian or eq25"),
+    # Eq 25: W of the differentiated species in place of the row species
+    ("jacobian_wrong_molar_mass",
+     "A[(size_t)ki * n_s + kc] += m->W[ki] / rho * m->nu[i] * damp * dq;",
+     "A[(size_t)ki * n_s + kc] += m->W[kc] / rho * m->nu[i] * damp * dq;",
+     "jacobian or eq25"),
 ]
 
 

@@ -69,6 +69,21 @@ MUTATIONS = [
      "h_RT[k] = y[n_s + k] / T;",
      "h_RT[k] = y[n_s + k];",
      "ann_thermo_mode"),
+    # Sec 3 network training: tanh' taken as 1 - a instead of 1 - a^2
+    ("mlp_tanh_derivative",
+     "d2[v] = s * (1.0 - a2[v] * a2[v]);",
+     "d2[v] = s * (1.0 - a2[v]);",
+     "mlp_gradient"),
+    # back-propagation through the transposed hidden weights
+    ("mlp_backward_transposed",
+     "for (int u = 0; u < H; ++u) s += W2[u * H + v] * d2[u];",
+     "for (int u = 0; u < H; ++u) s += W2[v * H + u] * d2[u];",
+     "mlp_gradient"),
+    # Adam without the first-moment bias correction
+    ("adam_no_bias_correction",
+     "double mhat = m1[i] / c1;",
+     "double mhat = m1[i];",
+     "adam"),
     # Eq 25: the reverse rate's derivative with the wrong sign
     ("jacobian_reverse_sign",
      "double dq = forward ? kf * d : -kr * d;",

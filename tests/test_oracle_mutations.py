@@ -69,6 +69,21 @@ MUTATIONS = [
      "h_RT[k] = y[n_s + k] / T;",
      "h_RT[k] = y[n_s + k];",
      "ann_thermo_mode"),
+    # Eq 1: every species' rate of change limits the step, not only consumption
+    ("eq1_any_sign",
+     "double rstar = fmax(-dYdt[k], 1.0e-30);",
+     "double rstar = fmax(fabs(dYdt[k]), 1.0e-30);",
+     "t3 or t1 or t8"),
+    # Eq 4: no cap at delta_max of the flow step
+    ("eq4_cap_dropped",
+     "double h = fmin(tstar, dtmax);",
+     "double h = tstar;",
+     "t4 or t1"),
+    # Eq 5 without the clamp to the end of the flow step
+    ("no_end_clamp",
+     "return fmin(h, tf - t);",
+     "return h;",
+     "last_step"),
     # Sec 3 network training: tanh' taken as 1 - a instead of 1 - a^2
     ("mlp_tanh_derivative",
      "d2[v] = s * (1.0 - a2[v] * a2[v]);",

@@ -96,6 +96,24 @@ def test_t3_stiff_decay_step_limiter(orc):
 
 
 # ----------------------------------------------------------------------------
+# Eqs 3-5 at the end of the flow step: the last step is cut to tf - t.  A
+# first-order decay A -> B whose Eq 3 step 0.9/k does not divide tf takes two
+# full steps (each leaves 0.1 of A) and one cut to half a step (leaves
+# 1 - 0.45 = 0.55 of A).
+# ----------------------------------------------------------------------------
+def test_last_step_is_cut_to_the_end_of_the_flow_step(orc):
+    k = 1.0e3
+    om = orc.OracleMech(tm.decay_ab(k))
+    tf = 2.5 * 0.9 / k
+    y0 = 0.5
+    r = orc.integrate_cell(om, 1000.0, P1, [y0, 1.0 - y0], tf, alpha=0.0, ystep_max=1.0,
+                           delta_max=1.0, dft_window=0)
+    assert r["iters"] == 3 and r["status"] == 0
+    assert r["Y"][0] == pytest.approx(y0 * 0.1 * 0.1 * 0.55, rel=1e-12)
+    assert r["Y"].sum() == pytest.approx(1.0, abs=1e-15)
+
+
+# ----------------------------------------------------------------------------
 # T4: Eq 4, Sec 2.4 -- frozen cells take exactly the iterations of the pure
 # time recurrence t += min(dt_max, tf - t) (brute-force count in FP64)
 # ----------------------------------------------------------------------------

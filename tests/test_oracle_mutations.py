@@ -84,6 +84,26 @@ MUTATIONS = [
      "return fmin(h, tf - t);",
      "return h;",
      "last_step"),
+    # Eq 13 without its lower bound on rOF
+    ("rof_floor_dropped",
+     "return fmax(r, p->rof_min);",
+     "return r;",
+     "t7_rof_sequences"),
+    # the energy equation with the wrong sign
+    ("energy_sign",
+     "*dTdt = -T * sum_hw / (rho * cpmix_R);",
+     "*dTdt = T * sum_hw / (rho * cpmix_R);",
+     "energy_equation"),
+    # Eqs 6-7: gamma left out of the rate-law concentrations
+    ("gamma_dropped_from_rates",
+     "C[k] = rho * orc_ystarstar(Y[k], p->alpha) / m->W[k];\n  }\n  if (m->mlp_prm",
+     "C[k] = rho * Y[k] / m->W[k];\n  }\n  if (m->mlp_prm",
+     "t9 or t11"),
+    # cm-mol-s to SI: one power of 1e-6 too many
+    ("arrhenius_units",
+     "double A_SI = m->A[j] * pow(1e-6, m_f - 1.0);\n    double kf = A_SI * pow(T, m->b[j]) * exp(-m->Ea[j] / (ORC_R * T));\n    double prod_f",
+     "double A_SI = m->A[j] * pow(1e-6, m_f);\n    double kf = A_SI * pow(T, m->b[j]) * exp(-m->Ea[j] / (ORC_R * T));\n    double prod_f",
+     "unit_conversion or t1"),
     # Sec 3 network training: tanh' taken as 1 - a instead of 1 - a^2
     ("mlp_tanh_derivative",
      "d2[v] = s * (1.0 - a2[v] * a2[v]);",

@@ -3,8 +3,10 @@
 Each case plants one mistake in a copy of the oracle's C source (a reading
 of the paper flipped, a sign or an index changed), builds it with gcc in a
 temporary folder, and runs the pins in a child process against that build
-(``STEV_ORACLE_LIB``).  The case passes when at least one of the named pins
-fails.  Nothing here touches the committed oracle or any GPU code.
+(``STEV_ORACLE_LIB``); the Python Levenberg-Marquardt oracle is mutated in a
+copy of ``oracle/`` and ``tests/`` in a temporary folder.  The case passes
+when at least one of the named pins fails.  Nothing here touches the
+committed oracle or any GPU code.
 """
 
 import os
@@ -242,5 +244,50 @@ def test_c3m_pins_catch_planted_mistake(tmp_path, name, old, new, pins):
     r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider",
                         os.path.join(ROOT, "tests", "test_oracle_c3m.py"), "-k", pins],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
+    assert r.returncode == 1 and "failed" in r.stdout, (
+        f"pins '{pins}' did not catch {name}:\n{r.stdout[-2000:]}")
+
+
+SRC_LMA = os.path.join(ROOT, "oracle", "ann_lma.py")
+
+# the same for the Levenberg-Marquardt oracle of the paper's network (Python):
+# the mutated module runs from a copy of oracle/ and tests/ in a temporary
+# folder, caught by tests/test_oracle_lma.py
+LMA_MUTATIONS = [
+    # the sigmoid's derivative taken as a instead of a (1 - a)
+    ("lma_sigmoid_derivative",
+     "ds = a * (1.0 - a)",
+     "ds = a",
+     "central_differences"),
+    # the residual with the wrong sign (J^T r then points uphill)
+    ("lma_residual_sign",
+     "r = forward(prm, H, n_out, xs) - target[s0:s0 + chunk]",
+     "r = target[s0:s0 + chunk] - forward(prm, H, n_out, xs)",
+     "least_squares_step"),
+    # Levenberg's identity in place of the scaled diagonal
+    ("lma_damping_identity",
+     "return dg + mu * np.mean(dg)",
+     "return np.ones_like(dg)",
+     "damping"),
+    # lambda raised after an accepted step as well as after a rejected one
+    ("lma_lambda_never_lowered",
+     "lam /= down",
+     "lam *= down",
+     "fits_a_known"),
+]
+
+
+@pytest.mark.parametrize("name,old,new,pins", LMA_MUTATIONS, ids=[m[0] for m in LMA_MUTATIONS])
+def test_lma_pins_catch_planted_mistake(tmp_path, name, old, new, pins):
+    with open(SRC_LMA) as f:
+        text = f.read()
+    assert text.count(old) == 1, f"mutation site for {name} not unique/found"
+    skip = shutil.ignore_patterns("__pycache__", "*.so", "*.tmp")
+    shutil.copytree(os.path.join(ROOT, "oracle"), str(tmp_path / "oracle"), ignore=skip)
+    shutil.copytree(os.path.join(ROOT, "tests"), str(tmp_path / "tests"), ignore=skip)
+    (tmp_path / "oracle" / "ann_lma.py").write_text(text.replace(old, new))
+    r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider",
+                        str(tmp_path / "tests" / "test_oracle_lma.py"), "-k", pins],
+                       cwd=str(tmp_path), capture_output=True, text=True, timeout=600)
     assert r.returncode == 1 and "failed" in r.stdout, (
         f"pins '{pins}' did not catch {name}:\n{r.stdout[-2000:]}")

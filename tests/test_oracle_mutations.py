@@ -106,6 +106,16 @@ MUTATIONS = [
      "double A_SI = m->A[j] * pow(1e-6, m_f - 1.0);\n    double kf = A_SI * pow(T, m->b[j]) * exp(-m->Ea[j] / (ORC_R * T));\n    double prod_f",
      "double A_SI = m->A[j] * pow(1e-6, m_f);\n    double kf = A_SI * pow(T, m->b[j]) * exp(-m->Ea[j] / (ORC_R * T));\n    double prod_f",
      "unit_conversion or t1"),
+    # Eq 16: h/RT with a3 T^2 / 2 in place of a3 T^2 / 3
+    ("enthalpy_coefficient",
+     "a[2] * T2 / 3.0 + a[3] * T3 / 4.0 +\n           a[4] * T4 / 5.0 + a[5] / T;",
+     "a[2] * T2 / 2.0 + a[3] * T3 / 4.0 +\n           a[4] * T4 / 5.0 + a[5] / T;",
+     "thermo_identities"),
+    # s/R without the a7 constant (the reverse rates' K then loses it)
+    ("entropy_constant_dropped",
+     "a[4] * T4 / 4.0 + a[6];",
+     "a[4] * T4 / 4.0;",
+     "t8 or thermo_identities"),
     # Sec 3 network training: tanh' taken as 1 - a instead of 1 - a^2
     ("mlp_tanh_derivative",
      "d2[v] = s * (1.0 - a2[v] * a2[v]);",

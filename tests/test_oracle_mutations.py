@@ -193,6 +193,26 @@ C3M_MUTATIONS = [
      "double r_eff = (j == R_WGS) ? rof * r[j] : r[j];",
      "double r_eff = (j == R_WGS || j == R_HOX) ? rof * r[j] : r[j];",
      "damping_applies"),
+    # Eq 43: the forward and reverse WGS constants swapped
+    ("wgs_constants_swapped",
+     "(c->Kf_wgs * pos(X_g[G_CO])",
+     "(c->Kr_wgs * pos(X_g[G_CO])",
+     "wgs_closed_form"),
+    # Eq 47: the H2 inhibition term added instead of dividing
+    ("stg_inhibition_sign",
+     "(1.0 + c->Fp_stg * (MW_g",
+     "(1.0 - c->Fp_stg * (MW_g",
+     "pressure_orders"),
+    # Eq 50: the O2 partial-pressure order 0.5 instead of 0.73
+    ("cox_order",
+     "pos(X_g[G_O2]) / 31.9988, 0.73)",
+     "pos(X_g[G_O2]) / 31.9988, 0.5)",
+     "pressure_orders"),
+    # Eq 55: the gas density to the power of the O2 order
+    ("meox_density_power",
+     "ep_g * pow(rho_g, 1.5) *\n              pow(pos(X_g[G_O2]), 1.3)",
+     "ep_g * pow(rho_g, 1.3) *\n              pow(pos(X_g[G_O2]), 1.3)",
+     "gas_density_orders"),
     # Eq 8 on WGS: the ring stores the damped rate rOF r h
     ("c3m_ring_stores_damped_rate",
      "ring[(int)((it - 1) % W)] = r[R_WGS] * h;",

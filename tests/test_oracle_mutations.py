@@ -116,6 +116,11 @@ MUTATIONS = [
      "a[4] * T4 / 4.0 + a[6];",
      "a[4] * T4 / 4.0;",
      "t8 or thermo_identities"),
+    # Eq 25: d(C^o)/dY without the gamma factor's (Y + 2 alpha) / (alpha + Y)
+    ("jacobian_gamma_factor_dropped",
+     "return pow(rho / W, o) * o * pow(Y, 2.0 * o - 1.0) * (Y + 2.0 * alpha) *\n         pow(alpha + Y, -(1.0 + o));",
+     "return pow(rho / W, o) * o * pow(Y, 2.0 * o - 1.0) * pow(alpha + Y, -o);",
+     "jacobian"),
     # Sec 3 network training: tanh' taken as 1 - a instead of 1 - a^2
     ("mlp_tanh_derivative",
      "d2[v] = s * (1.0 - a2[v] * a2[v]);",

@@ -57,3 +57,13 @@ def test_fields_and_batches_have_the_stated_shape():
     assert np.all(Y6[:, 5] >= 0.5 - 1e-12)
     sizes = synth.batch_sizes(64, 256, 131072, seed=103)
     assert len(sizes) == 64 and sizes.min() >= 256 and sizes.max() <= 131072
+
+
+def test_c3m_cells_are_consistent_gas_solid_states():
+    st = synth.make_c3m_cells(2048, seed=108)
+    assert st.shape == (2048, 26)
+    # volume fractions add to one; each phase's mass fractions add to one
+    np.testing.assert_allclose(st[:, 3] + st[:, 5], 1.0, atol=1e-15)
+    np.testing.assert_allclose(st[:, 8:22].sum(axis=1), 1.0, atol=1e-12)
+    np.testing.assert_allclose(st[:, 22:26].sum(axis=1), 1.0, atol=1e-12)
+    assert np.all(st[:, 8:26] >= 0.0) and np.all(st[:, [0, 1, 2, 4, 6, 7]] > 0.0)

@@ -81,7 +81,9 @@ typedef struct {
   double r_fac;           /* Eq 12 damping factor, > 1              (2.0)  */
   double rof_min;         /* floor of rOF, > 0                      (1e-12) */
   int32_t dft_window;     /* Eq 8 ring length: 13, or 0 to disable  (13)   */
-  int32_t lanes_per_cell; /* 0 auto, else 1|8|16|32|64                      */
+  int32_t lanes_per_cell; /* 0 auto, else 1|4|8|16|32|64; a value whose
+                             kernel variant cannot hold the mechanism gives
+                             STEV_EINVAL                                    */
   int64_t max_iters;      /* per-cell iteration cap -> status 2     (1e6)  */
   int32_t waves_per_wg;   /* 0 auto, else 1..4 waves per workgroup          */
   int32_t compact_every;  /* refill cadence K in iterations, 0 auto (64 with
